@@ -1,0 +1,130 @@
+"""Benchmark of the fused stream-and-collide step on one MI355X.
+
+Workload: the circular shock at 1024 x 1024 (periodic), Np = 4 radial shells x
+K = 64 angles (256 velocities), equilibrium order 3, FP32 populations, disc of
+radius 128 (n=1, T=1.5) in a background (n=0.5, T=1) with 1% seeded noise on
+n; two runs, Kn = 0.01 and Kn = 1.  A step is one fused stream-and-collide
+launch over the whole grid; the timed region holds `--steps` steps of each run
+with the populations already resident in HBM.
+
+Prints one JSON line with the throughput in site-velocity updates per second
+(GSVUPS), the roofline of the fused kernel (algorithmic bytes / launch time
+from HIP events on the library's stream, against the 8 TB/s HBM peak) and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "GSVUPS + % HBM roofline; coarse-angle+MLP vs fine-angle speedup at equal error"
+BYTES_PER_SV = {"f32": 8, "f64": 16}
+
+
+def gpu_run(cfg, steps, warmup, precision, waves):
+    import torch
+    from paper_2011_06856_amd import rlbm
+    s = rlbm.Solver(cfg["Np"], cfg["K"], cfg["N"])
+    s.init_fields(cfg["nx"], cfg["ny"], *cfg["fields"], tau=cfg["tau"], dt=cfg["dt"], precision=precision)
+    if waves:
+        s.set_waves(waves)
+    s.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms_events = s.step_timed(steps)   # HIP events on the library's stream around the launches
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n, eps, ux, uy, ch = s.moments()
+    ok = bool(np.isfinite(n).all() and np.isfinite(eps).all())
+    return dict(wall_s=wall, event_ms=ms_events, sv=float(cfg["nx"] * cfg["ny"] * s.nvel * steps),
+                waves=s.get_waves(), finite=ok, charges=ch.tolist())
+
+
+def cpu_baseline(precision_unused, budget_s):
+    """The FP64 oracle on a bounded sample: the same quadrature and state on a
+    256 x 256 grid (Kn = 0.01 with tau scaled to the side), steps sized to the
+    budget after one timed probe step."""
+    import oracle as O
+    side = 256
+    cfg = W.circular_shock(side, Kn=0.01, steps=1)
+    q = O.Quadrature(cfg["Np"], cfg["K"], cfg["N"])
+    sim = O.Sim(q, side, side, *cfg["fields"], tau=cfg["tau"], dt=cfg["dt"])
+    t0 = time.perf_counter()
+    sim.step(1)
+    probe = time.perf_counter() - t0
+    nsteps = max(1, int(budget_s / max(probe, 1e-3)))
+    t0 = time.perf_counter()
+    sim.step(nsteps)
+    dt = time.perf_counter() - t0
+    sv = side * side * q.nvel * nsteps
+    return dict(value=sv / dt / 1e9, unit="GSVUPS", cores=O.num_threads(), kind="oracle",
+                sample="%dx%d grid, Np=4 x K=64 (256 velocities), order 3, Kn=0.01, %d steps, FP64" % (side, side, nsteps))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--side", type=int, default=1024)
+    ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    runs = {}
+    for Kn in (0.01, 1.0):
+        cfg = W.circular_shock(a.side, Kn=Kn, steps=a.steps)
+        print("bench: run Kn=%g %s steps=%d" % (Kn, cfg["name"], a.steps), file=sys.stderr, flush=True)
+        runs[Kn] = gpu_run(cfg, a.steps, a.warmup, a.precision, a.waves)
+    sv = sum(r["sv"] for r in runs.values())
+    wall = sum(r["wall_s"] for r in runs.values())
+    ev_ms = sum(r["event_ms"] for r in runs.values())
+    launches = 2 * a.steps
+    launch_ms = ev_ms / launches
+    bytes_per_launch = BYTES_PER_SV[a.precision] * sv / launches
+    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": sv / wall / 1e9,
+        "unit": "GSVUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * wall / launches,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": a.precision,
+        "data": "synthetic",
+        "config": {"workload": "circular_shock_%d_np4_k64_order3" % a.side, "grid": [a.side, a.side],
+                   "velocities": 256, "Kn": [0.01, 1.0], "runs": 2, "steps_per_run": a.steps,
+                   "waves_per_group": runs[0.01]["waves"], "fields_finite": all(r["finite"] for r in runs.values())},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_stream_collide", "algorithmic_bytes_per_sv": BYTES_PER_SV[a.precision],
+                     "avg_launch_ms": launch_ms},
+    }
+    if not a.no_cpu_baseline:
+        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(a.precision, a.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,183 @@
+/*
+ * rlbm.h -- C ABI of the MI355X (gfx950) relativistic lattice Boltzmann
+ * solver for massless particles in (2+1) dimensions.
+ *
+ * The method is that of Bazzanini, Gabbana, Simeoni, Succi and Tripiccione,
+ * "A Lattice Boltzmann Method for Relativistic Rarefied Flows in (2+1)
+ * Dimensions" (arXiv:2011.06856):
+ *   - discrete velocities from the product quadrature of Sec. 2.3, Eq.
+ *     off-lattice-quad: Np radial Gauss-Laguerre shells times K equispaced
+ *     angles, shell i rotated by i/Np of the angular spacing; every velocity
+ *     has unit speed and none lies on the lattice;
+ *   - one time step (Eq. discrete-rbe) = bilinear upwind streaming (Eq.
+ *     streaming, Eq. interpolation), moments (Eq. discrete_sum_moments),
+ *     Landau-frame solve (eps U^a = T^{ab} U_b, eps = 2P = 2nT), the truncated
+ *     Maxwell-Juttner equilibrium of order N (Eq. mj-feq-expansion-truncated)
+ *     and Anderson-Witting relaxation (Eq. collision, with the relaxing sign of
+ *     Eq. discrete-rbe), fused into one kernel.
+ *
+ * Units: lattice units, dx = dy = 1, c = 1, weighting temperature T0 = 1.
+ * Grids are [ny][nx] row-major.  Velocity index v = i*K + j (shell i, angle j).
+ * Populations live on the device as f[v][y][x] (structure of arrays).
+ *
+ * Every call returns an int status: RLBM_OK (0) or a negative error code; no
+ * exception crosses the ABI.  rlbm_last_error() gives a message for the last
+ * failing call on a context.  One host thread may use a context at a time;
+ * distinct contexts are independent.
+ */
+#ifndef RLBM_H
+#define RLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rlbm_ctx_s* rlbm_ctx;
+
+enum {
+    RLBM_OK = 0,
+    RLBM_EINVAL = -1,   /* invalid argument; nothing was changed */
+    RLBM_ENOMEM = -2,   /* device allocation failed or workspace too small */
+    RLBM_EDEVICE = -3,  /* a HIP call failed (no device, launch failure) */
+    RLBM_ENONPHYS = -4, /* some site had no physical Landau frame (sticky) */
+    RLBM_ESTATE = -5    /* call out of order (e.g. step before init_fields) */
+};
+
+enum { RLBM_F64 = 0, RLBM_F32 = 1, RLBM_BF16DEV = 2 };   /* population storage */
+enum { RLBM_BC_PERIODIC = 0, RLBM_BC_CLAMP = 1 };         /* per axis */
+
+/*
+ * Build the quadrature of Sec. 2.3 (Eq. off-lattice-quad) on the host and
+ * create a context.  No device call is made.
+ *   n_radial  Np >= 1 shells at the roots of L_Np, weights
+ *             p_i / ((Np+1)^2 L_{Np+1}(p_i)^2);
+ *   n_angle   K angles per shell, K >= 2N+1 (exactness of the angular rule);
+ *   order     N >= 1, order of the equilibrium expansion, N <= 7, and
+ *             Np >= ceil((N+3)/2) so that N^mu and T^{mu nu} of f_eq are exact;
+ *   rotate    1: theta_ij = (j + i/Np) 2 pi / K; 0: theta_ij = 2 pi j / K.
+ * On success *out owns host memory released by rlbm_destroy.
+ * Errors: RLBM_EINVAL for out == NULL or any bound above.
+ */
+int rlbm_init_quadrature(rlbm_ctx* out, int n_radial, int n_angle, int order, int rotate);
+
+/* Number of discrete velocities Np*K of the context. */
+int rlbm_nvel(rlbm_ctx ctx);
+
+/*
+ * Copy the quadrature out: p[v] = p^0 (shell energy), theta[v], w[v] (weights
+ * summing to 2 pi).  Each pointer is a caller-owned host array of rlbm_nvel()
+ * doubles, or NULL to skip it.
+ */
+int rlbm_get_quadrature(rlbm_ctx ctx, double* p, double* theta, double* w);
+
+/* Device workspace in bytes needed by rlbm_init_fields for an nx x ny grid at
+ * the given precision (two population buffers plus per-site scratch). */
+int rlbm_workspace_bytes(rlbm_ctx ctx, int nx, int ny, int precision, size_t* bytes);
+
+/*
+ * Set the initial populations to the truncated equilibrium of the given
+ * fields (a fluid whose sites are each in local equilibrium; Sec. 3) and fix
+ * the run parameters.
+ *   n, T, ux, uy  host arrays [ny][nx], caller-owned, read only during the
+ *                 call: density, temperature and the spatial components U^i of
+ *                 the four-velocity; ux/uy may be NULL (zero).  Rejected with
+ *                 RLBM_EINVAL unless finite, n > 0, T > 0.
+ *   tau           proper relaxation time > 0 (Eq. boltz_eq); +inf = free
+ *                 streaming.  Kn = tau / L (Sec. 3.1).
+ *   dt            time step in (0, 1] (the bilinear weights dt |v_x|, dt |v_y|
+ *                 must stay in [0, 1]).
+ *   bc_x, bc_y    RLBM_BC_PERIODIC or RLBM_BC_CLAMP (zero-gradient: the
+ *                 upwind neighbour outside the grid is the edge cell).
+ *   precision     RLBM_F64 or RLBM_F32 population storage; RLBM_BF16DEV stores
+ *                 f - f_eq in bfloat16 with per-site equilibrium coefficients.
+ *   d_workspace   device memory of at least rlbm_workspace_bytes() bytes,
+ *                 256-byte aligned, owned by the caller (e.g. a torch tensor)
+ *                 and alive until rlbm_destroy; NULL lets the library
+ *                 allocate and own it.
+ *   hip_stream    hipStream_t for all work of this context; NULL = default.
+ * May be called again to restart a context (same or different grid).
+ */
+int rlbm_init_fields(rlbm_ctx ctx, int nx, int ny,
+                     const double* n, const double* T, const double* ux, const double* uy,
+                     double tau, double dt, int bc_x, int bc_y, int precision,
+                     void* d_workspace, void* hip_stream);
+
+/*
+ * Advance nsteps >= 0 time steps (Eq. discrete-rbe), one fused
+ * stream-and-collide launch per step, asynchronously on the context's
+ * stream.  Allocates nothing.  Non-physical sites (no timelike Landau
+ * eigenvector, n <= 0 or eps <= 0) are streamed without collision and raise a
+ * sticky device flag reported by the next rlbm_moments.
+ */
+int rlbm_step(rlbm_ctx ctx, int nsteps);
+
+/*
+ * Like rlbm_step, bracketing the launches with HIP events on the context's
+ * stream; synchronises and returns the elapsed milliseconds in *ms.
+ */
+int rlbm_step_timed(rlbm_ctx ctx, int nsteps, double* ms);
+
+/*
+ * Macroscopic fields of the current populations (moments, Eq.
+ * discrete_sum_moments, then the Landau frame, all in FP64): n, eps = T^{ab}
+ * U_a U_b, ux = U^x, uy = U^y, each a caller-owned host array [ny][nx] or
+ * NULL; charges = {sum N^0, sum T^00, sum T^0x, sum T^0y} over the grid
+ * (4 doubles) or NULL.  Synchronises the stream.  Returns RLBM_ENONPHYS if any
+ * step or this call met a non-physical site (the outputs are still written;
+ * such sites hold NaN); the flag is then cleared.
+ */
+int rlbm_moments(rlbm_ctx ctx, double* n, double* eps, double* ux, double* uy, double* charges);
+
+/* Checkpoint: copy the current populations (storage precision, layout
+ * f[v][y][x]) to / from a caller-owned host buffer of exactly
+ * nvel * nx * ny * element-size bytes (8 for F64, 4 for F32, 2 for BF16DEV
+ * deviations followed by the per-site coefficients); other sizes give
+ * RLBM_EINVAL.  Synchronous. */
+int rlbm_populations_bytes(rlbm_ctx ctx, size_t* bytes);
+int rlbm_get_populations(rlbm_ctx ctx, void* host, size_t bytes);
+int rlbm_set_populations(rlbm_ctx ctx, const void* host, size_t bytes);
+
+/*
+ * Kernel shape: waves per work-group (1..16) of the fused kernel, 0 = the
+ * built-in choice.  Results do not depend on it beyond rounding order.  Used
+ * by the autotuner and by tile-shape tests.  RLBM_EINVAL if unsupported.
+ */
+int rlbm_set_waves(rlbm_ctx ctx, int waves);
+int rlbm_get_waves(rlbm_ctx ctx, int* waves);
+
+/*
+ * Host-side evaluations with the context's own tables; no device call is
+ * made, so they run without a GPU.
+ *   rlbm_host_feq     the discrete truncated equilibrium f_eq_v of fields
+ *                     (n, T, U^x, U^y) (Eq. mj-feq-expansion-truncated) into a
+ *                     caller-owned array of rlbm_nvel() doubles;
+ *   rlbm_host_landau  the Landau frame (eps U^a = T^{ab} U_b, eps = 2nT) of
+ *                     mom9 = (N^0, N^x, N^y, T^00, T^0x, T^0y, T^xx, T^xy,
+ *                     T^yy): out6 = (n, eps, U^x, U^y, T, U^0); returns
+ *                     RLBM_ENONPHYS for a state without a physical frame.
+ */
+int rlbm_host_feq(rlbm_ctx ctx, double n, double T, double ux, double uy, double* feq);
+int rlbm_host_landau(const double* mom9, double* out6);
+
+/*
+ * The Landau frame evaluated by the device code of the kernels for count
+ * moment sets: mom = host [count][9] as for rlbm_host_landau, out = host
+ * [count][7] = (n, eps, U^x, U^y, T, U^0, ok).  Synchronous on the default
+ * stream; allocates and frees its own device scratch.  RLBM_EDEVICE on a HIP
+ * failure.  A check of the device arithmetic, not part of the time step.
+ */
+int rlbm_device_landau(int count, const double* mom, double* out);
+
+/* Message for the last failing call on ctx (static storage of the context). */
+const char* rlbm_last_error(rlbm_ctx ctx);
+
+/* Release the context, its tables and any library-owned workspace. */
+int rlbm_destroy(rlbm_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RLBM_H */

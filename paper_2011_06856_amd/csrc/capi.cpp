@@ -1,0 +1,429 @@
+// capi.cpp -- the C ABI declared in include/rlbm.h.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "rlbm_internal.h"
+
+struct rlbm_ctx_s {
+    HostQuad q;
+    std::string err;
+    int have_fields = 0;
+    int nx = 0, ny = 0, prec = RLBM_F64, bcx = 0, bcy = 0;
+    long long S = 0;
+    double tau = 0, dt = 1, rate = 0;
+    int waves = 0;
+    hipStream_t st = nullptr;
+    char* ws = nullptr;
+    bool ws_owned = false;
+    size_t ws_bytes = 0;
+    void* f[2] = {nullptr, nullptr};
+    int cur = 0;
+    double* d_fields = nullptr;
+    double* d_partials = nullptr;
+    int* d_flag = nullptr;
+    void* d_vel = nullptr;               // VelRec<TC>
+    VelRec<double>* d_veld = nullptr;    // FP64 table for init and fields
+    double* d_G = nullptr;
+    double* d_Pc = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    long long steps = 0;
+};
+
+namespace {
+
+int fail(rlbm_ctx c, int code, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_fail(rlbm_ctx c, hipError_t e, const char* where)
+{
+    return fail(c, RLBM_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+size_t elem_size(int prec) { return prec == RLBM_F64 ? 8 : (prec == RLBM_F32 ? 4 : 2); }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t f0, f1, fields, partials, flag, total;
+};
+
+Layout layout(int nvel, long long S, int prec)
+{
+    Layout L;
+    const size_t fb = align256((size_t)nvel * S * elem_size(prec));
+    L.f0 = 0;
+    L.f1 = L.f0 + fb;
+    L.fields = L.f1 + fb;
+    L.partials = L.fields + align256((size_t)4 * S * sizeof(double));
+    L.flag = L.partials + align256((size_t)fields_blocks(S) * 4 * sizeof(double));
+    L.total = L.flag + 256;
+    return L;
+}
+
+int nmax_of(int N) { return N <= 3 ? 3 : (N <= 5 ? 5 : 7); }
+
+void free_tables(rlbm_ctx c)
+{
+    if (c->d_vel) (void)hipFree(c->d_vel);
+    if (c->d_veld) (void)hipFree(c->d_veld);
+    if (c->d_G) (void)hipFree(c->d_G);
+    if (c->d_Pc) (void)hipFree(c->d_Pc);
+    c->d_vel = nullptr; c->d_veld = nullptr; c->d_G = nullptr; c->d_Pc = nullptr;
+}
+
+bool finite_arr(const double* a, long long S)
+{
+    for (long long i = 0; i < S; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rlbm_init_quadrature(rlbm_ctx* out, int n_radial, int n_angle, int order, int rotate)
+{
+    if (!out) return RLBM_EINVAL;
+    *out = nullptr;
+    rlbm_ctx c = new (std::nothrow) rlbm_ctx_s();
+    if (!c) return RLBM_ENOMEM;
+    std::string err;
+    const int rc = build_host_quad(c->q, n_radial, n_angle, order, rotate, err);
+    if (rc != RLBM_OK) {
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return RLBM_OK;
+}
+
+int rlbm_nvel(rlbm_ctx c) { return c ? c->q.nvel : RLBM_EINVAL; }
+
+int rlbm_get_quadrature(rlbm_ctx c, double* p, double* theta, double* w)
+{
+    if (!c) return RLBM_EINVAL;
+    for (int v = 0; v < c->q.nvel; ++v) {
+        if (p) p[v] = c->q.p[v];
+        if (theta) theta[v] = c->q.theta[v];
+        if (w) w[v] = c->q.w[v];
+    }
+    return RLBM_OK;
+}
+
+int rlbm_workspace_bytes(rlbm_ctx c, int nx, int ny, int precision, size_t* bytes)
+{
+    if (!c || !bytes || nx < 1 || ny < 1) return fail(c, RLBM_EINVAL, "workspace_bytes: bad arguments");
+    if (precision != RLBM_F64 && precision != RLBM_F32) return fail(c, RLBM_EINVAL, "unsupported precision");
+    *bytes = layout(c->q.nvel, (long long)nx * ny, precision).total;
+    return RLBM_OK;
+}
+
+int rlbm_init_fields(rlbm_ctx c, int nx, int ny, const double* n, const double* T, const double* ux,
+                     const double* uy, double tau, double dt, int bc_x, int bc_y, int precision,
+                     void* d_workspace, void* hip_stream)
+{
+    if (!c) return RLBM_EINVAL;
+    if (nx < 1 || ny < 1 || (long long)nx * ny > (1LL << 31)) return fail(c, RLBM_EINVAL, "grid size out of range");
+    if (!n || !T) return fail(c, RLBM_EINVAL, "n and T are required");
+    if (!(tau > 0.0) || std::isnan(tau)) return fail(c, RLBM_EINVAL, "tau must be > 0 (inf allowed)");
+    if (!(dt > 0.0 && dt <= 1.0)) return fail(c, RLBM_EINVAL, "dt must be in (0, 1]");
+    if ((bc_x != RLBM_BC_PERIODIC && bc_x != RLBM_BC_CLAMP) || (bc_y != RLBM_BC_PERIODIC && bc_y != RLBM_BC_CLAMP))
+        return fail(c, RLBM_EINVAL, "bad boundary condition");
+    if (precision != RLBM_F64 && precision != RLBM_F32) return fail(c, RLBM_EINVAL, "unsupported precision");
+    if (d_workspace && ((uintptr_t)d_workspace & 255)) return fail(c, RLBM_EINVAL, "workspace must be 256-byte aligned");
+    const long long S = (long long)nx * ny;
+    if (!finite_arr(n, S) || !finite_arr(T, S) || (ux && !finite_arr(ux, S)) || (uy && !finite_arr(uy, S)))
+        return fail(c, RLBM_EINVAL, "fields must be finite");
+    for (long long i = 0; i < S; ++i)
+        if (!(n[i] > 0.0) || !(T[i] > 0.0)) return fail(c, RLBM_EINVAL, "n and T must be positive");
+
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(c, e, "hipGetDevice");
+    const Layout L = layout(c->q.nvel, S, precision);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+
+    if (d_workspace) {
+        if (c->ws_owned && c->ws) (void)hipFree(c->ws);
+        c->ws = static_cast<char*>(d_workspace);
+        c->ws_owned = false;
+        c->ws_bytes = L.total;
+    } else if (!c->ws_owned || c->ws_bytes < L.total) {
+        if (c->ws_owned && c->ws) (void)hipFree(c->ws);
+        c->ws = nullptr;
+        c->ws_owned = false;
+        void* p = nullptr;
+        e = hipMalloc(&p, L.total);
+        if (e != hipSuccess) return fail(c, RLBM_ENOMEM, "hipMalloc of the workspace failed");
+        c->ws = static_cast<char*>(p);
+        c->ws_owned = true;
+        c->ws_bytes = L.total;
+    }
+    c->nx = nx; c->ny = ny; c->S = S; c->prec = precision;
+    c->bcx = bc_x; c->bcy = bc_y; c->tau = tau; c->dt = dt;
+    c->rate = std::isinf(tau) ? 0.0 : dt / tau;
+    c->st = st;
+    c->f[0] = c->ws + L.f0;
+    c->f[1] = c->ws + L.f1;
+    c->d_fields = reinterpret_cast<double*>(c->ws + L.fields);
+    c->d_partials = reinterpret_cast<double*>(c->ws + L.partials);
+    c->d_flag = reinterpret_cast<int*>(c->ws + L.flag);
+    c->cur = 0;
+    c->steps = 0;
+
+    // device tables
+    free_tables(c);
+    std::vector<VelRec<double>> vd;
+    build_vel_table(c->q, dt, vd);
+    const size_t nv = c->q.nvel;
+    if ((e = hipMalloc(&c->d_veld, nv * sizeof(VelRec<double>))) != hipSuccess) return fail(c, RLBM_ENOMEM, "table alloc");
+    if ((e = hipMalloc(&c->d_G, c->q.G.size() * sizeof(double))) != hipSuccess) return fail(c, RLBM_ENOMEM, "table alloc");
+    if ((e = hipMalloc(&c->d_Pc, c->q.Pc.size() * sizeof(double))) != hipSuccess) return fail(c, RLBM_ENOMEM, "table alloc");
+    if ((e = hipMemcpy(c->d_veld, vd.data(), nv * sizeof(VelRec<double>), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(c, e, "table upload");
+    if ((e = hipMemcpy(c->d_G, c->q.G.data(), c->q.G.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(c, e, "table upload");
+    if ((e = hipMemcpy(c->d_Pc, c->q.Pc.data(), c->q.Pc.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(c, e, "table upload");
+    if (precision == RLBM_F64) {
+        void* p = nullptr;   // the kernel's own copy, so that each table has one owner
+        if ((e = hipMalloc(&p, nv * sizeof(VelRec<double>))) != hipSuccess) return fail(c, RLBM_ENOMEM, "table alloc");
+        if ((e = hipMemcpy(p, vd.data(), nv * sizeof(VelRec<double>), hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(c, e, "table upload");
+        c->d_vel = p;
+    } else {
+        std::vector<VelRec<float>> vf(nv);
+        for (size_t v = 0; v < nv; ++v) {
+            const double* s = reinterpret_cast<const double*>(&vd[v]);
+            float* d = reinterpret_cast<float*>(&vf[v]);
+            for (int k = 0; k < 32; ++k) d[k] = (float)s[k];
+        }
+        void* p = nullptr;
+        if ((e = hipMalloc(&p, nv * sizeof(VelRec<float>))) != hipSuccess) return fail(c, RLBM_ENOMEM, "table alloc");
+        if ((e = hipMemcpy(p, vf.data(), nv * sizeof(VelRec<float>), hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(c, e, "table upload");
+        c->d_vel = p;
+    }
+
+    // upload the fields and build f = f_eq
+    std::vector<double> h(4 * (size_t)S, 0.0);
+    std::memcpy(h.data(), n, S * sizeof(double));
+    std::memcpy(h.data() + S, T, S * sizeof(double));
+    if (ux) std::memcpy(h.data() + 2 * S, ux, S * sizeof(double));
+    if (uy) std::memcpy(h.data() + 3 * S, uy, S * sizeof(double));
+    if ((e = hipMemcpyAsync(c->d_fields, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st)) != hipSuccess)
+        return hip_fail(c, e, "field upload");
+    if ((e = hipMemsetAsync(c->d_flag, 0, sizeof(int), st)) != hipSuccess) return hip_fail(c, e, "flag clear");
+    e = launch_init(precision, nmax_of(c->q.N), c->d_fields, c->f[0], c->d_veld, c->d_G, c->d_Pc, nx, ny,
+                    c->q.nvel, c->q.K, c->q.Np, st);
+    if (e != hipSuccess) return hip_fail(c, e, "init kernel");
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(c, e, "init sync");
+    if (!c->ev0) {
+        if ((e = hipEventCreate(&c->ev0)) != hipSuccess) return hip_fail(c, e, "event");
+        if ((e = hipEventCreate(&c->ev1)) != hipSuccess) return hip_fail(c, e, "event");
+    }
+    c->have_fields = 1;
+    return RLBM_OK;
+}
+
+int rlbm_set_waves(rlbm_ctx c, int waves)
+{
+    if (!c) return RLBM_EINVAL;
+    if (waves < 0 || waves > 16) return fail(c, RLBM_EINVAL, "waves must be in [0, 16]");
+    c->waves = waves;
+    return RLBM_OK;
+}
+
+int rlbm_get_waves(rlbm_ctx c, int* waves)
+{
+    if (!c || !waves) return RLBM_EINVAL;
+    *waves = c->waves ? c->waves : default_waves(c->prec, nmax_of(c->q.N), c->q.nvel);
+    return RLBM_OK;
+}
+
+int rlbm_step(rlbm_ctx c, int nsteps)
+{
+    if (!c) return RLBM_EINVAL;
+    if (!c->have_fields) return fail(c, RLBM_ESTATE, "rlbm_step before rlbm_init_fields");
+    if (nsteps < 0) return fail(c, RLBM_EINVAL, "nsteps < 0");
+    const int waves = c->waves ? c->waves : default_waves(c->prec, nmax_of(c->q.N), c->q.nvel);
+    SCParams p;
+    p.vel = c->d_vel;
+    p.G = c->d_G;
+    p.Pc = c->d_Pc;
+    p.nx = c->nx; p.ny = c->ny; p.nvel = c->q.nvel; p.K = c->q.K; p.Np = c->q.Np; p.N = c->q.N;
+    p.bcx = c->bcx; p.bcy = c->bcy; p.S = c->S; p.rate = c->rate; p.flag = c->d_flag;
+    p.chunk = (c->q.nvel + waves - 1) / waves;
+    for (int s = 0; s < nsteps; ++s) {
+        p.fin = c->f[c->cur];
+        p.fout = c->f[c->cur ^ 1];
+        const hipError_t e = launch_stream_collide(c->prec, nmax_of(c->q.N), waves, p, c->st);
+        if (e != hipSuccess) return hip_fail(c, e, "stream_collide launch");
+        c->cur ^= 1;
+        ++c->steps;
+    }
+    return RLBM_OK;
+}
+
+int rlbm_step_timed(rlbm_ctx c, int nsteps, double* ms)
+{
+    if (!c || !ms) return RLBM_EINVAL;
+    if (!c->have_fields) return fail(c, RLBM_ESTATE, "rlbm_step_timed before rlbm_init_fields");
+    hipError_t e = hipEventRecord(c->ev0, c->st);
+    if (e != hipSuccess) return hip_fail(c, e, "event record");
+    const int rc = rlbm_step(c, nsteps);
+    if (rc != RLBM_OK) return rc;
+    if ((e = hipEventRecord(c->ev1, c->st)) != hipSuccess) return hip_fail(c, e, "event record");
+    if ((e = hipEventSynchronize(c->ev1)) != hipSuccess) return hip_fail(c, e, "event sync");
+    float t = 0.f;
+    if ((e = hipEventElapsedTime(&t, c->ev0, c->ev1)) != hipSuccess) return hip_fail(c, e, "elapsed");
+    *ms = t;
+    return RLBM_OK;
+}
+
+int rlbm_moments(rlbm_ctx c, double* n, double* eps, double* ux, double* uy, double* charges)
+{
+    if (!c) return RLBM_EINVAL;
+    if (!c->have_fields) return fail(c, RLBM_ESTATE, "rlbm_moments before rlbm_init_fields");
+    hipError_t e = launch_fields(c->prec, c->f[c->cur], c->d_veld, c->d_fields, c->d_partials, c->d_flag, c->nx, c->ny,
+                                 c->q.nvel, c->st);
+    if (e != hipSuccess) return hip_fail(c, e, "fields launch");
+    const long long S = c->S;
+    double* outs[4] = {n, eps, ux, uy};
+    for (int k = 0; k < 4; ++k)
+        if (outs[k]) {
+            e = hipMemcpyAsync(outs[k], c->d_fields + k * S, S * sizeof(double), hipMemcpyDeviceToHost, c->st);
+            if (e != hipSuccess) return hip_fail(c, e, "fields copy");
+        }
+    const int nb = fields_blocks(S);
+    std::vector<double> part(4 * (size_t)nb);
+    e = hipMemcpyAsync(part.data(), c->d_partials, part.size() * sizeof(double), hipMemcpyDeviceToHost, c->st);
+    if (e != hipSuccess) return hip_fail(c, e, "charges copy");
+    int flag = 0;
+    if ((e = hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->st)) != hipSuccess)
+        return hip_fail(c, e, "flag copy");
+    if ((e = hipStreamSynchronize(c->st)) != hipSuccess) return hip_fail(c, e, "moments sync");
+    if (charges) {
+        long double acc[4] = {0, 0, 0, 0};
+        for (int b = 0; b < nb; ++b)
+            for (int k = 0; k < 4; ++k) acc[k] += part[4 * (size_t)b + k];
+        for (int k = 0; k < 4; ++k) charges[k] = (double)acc[k];
+    }
+    if (flag) {
+        if ((e = hipMemsetAsync(c->d_flag, 0, sizeof(int), c->st)) != hipSuccess) return hip_fail(c, e, "flag clear");
+        (void)hipStreamSynchronize(c->st);
+        return fail(c, RLBM_ENONPHYS, "non-physical state met (no timelike Landau frame, n <= 0 or eps <= 0)");
+    }
+    return RLBM_OK;
+}
+
+int rlbm_populations_bytes(rlbm_ctx c, size_t* bytes)
+{
+    if (!c || !bytes) return RLBM_EINVAL;
+    if (!c->have_fields) return fail(c, RLBM_ESTATE, "no populations yet");
+    *bytes = (size_t)c->q.nvel * c->S * elem_size(c->prec);
+    return RLBM_OK;
+}
+
+int rlbm_get_populations(rlbm_ctx c, void* host, size_t bytes)
+{
+    size_t need = 0;
+    int rc = rlbm_populations_bytes(c, &need);
+    if (rc != RLBM_OK) return rc;
+    if (!host || bytes != need) return fail(c, RLBM_EINVAL, "population buffer size mismatch");
+    hipError_t e = hipStreamSynchronize(c->st);
+    if (e == hipSuccess) e = hipMemcpy(host, c->f[c->cur], need, hipMemcpyDeviceToHost);
+    return e == hipSuccess ? RLBM_OK : hip_fail(c, e, "get_populations");
+}
+
+int rlbm_set_populations(rlbm_ctx c, const void* host, size_t bytes)
+{
+    size_t need = 0;
+    int rc = rlbm_populations_bytes(c, &need);
+    if (rc != RLBM_OK) return rc;
+    if (!host || bytes != need) return fail(c, RLBM_EINVAL, "population buffer size mismatch");
+    hipError_t e = hipStreamSynchronize(c->st);
+    if (e == hipSuccess) e = hipMemcpy(c->f[c->cur], host, need, hipMemcpyHostToDevice);
+    return e == hipSuccess ? RLBM_OK : hip_fail(c, e, "set_populations");
+}
+
+const char* rlbm_last_error(rlbm_ctx c)
+{
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+int rlbm_destroy(rlbm_ctx c)
+{
+    if (!c) return RLBM_EINVAL;
+    if (c->have_fields) (void)hipStreamSynchronize(c->st);
+    free_tables(c);
+    if (c->ws_owned && c->ws) (void)hipFree(c->ws);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    delete c;
+    return RLBM_OK;
+}
+
+// Host-side evaluations with the library's own tables (no device call): the
+// discrete equilibrium of given fields and the Landau frame of nine moments.
+int rlbm_host_feq(rlbm_ctx c, double n, double T, double ux, double uy, double* feq)
+{
+    if (!c || !feq) return RLBM_EINVAL;
+    std::vector<VelRec<double>> vd;
+    build_vel_table(c->q, 1.0, vd);
+    const double U0 = std::sqrt(1.0 + ux * ux + uy * uy);
+    const int GS = (RLBM_NMAX + 1) * (RLBM_NMAX + 1);
+    for (int i = 0; i < c->q.Np; ++i) {
+        double cf[RLBM_NT];
+        shell_coeffs<RLBM_NMAX>(c->q.G.data() + (size_t)i * GS, c->q.Pc.data(), n, T, U0, ux, uy,
+                                [&](int m, double cm, double sm) {
+                                    if (m == 0) {
+                                        cf[0] = cm;
+                                    } else {
+                                        cf[2 * m - 1] = cm;
+                                        cf[2 * m] = sm;
+                                    }
+                                });
+        for (int j = 0; j < c->q.K; ++j) {
+            const int v = i * c->q.K + j;
+            double fe = 0.0;
+            for (int t = 0; t < RLBM_NT; ++t) fe += cf[t] * vd[v].H[t];
+            feq[v] = fe;
+        }
+    }
+    return RLBM_OK;
+}
+
+int rlbm_host_landau(const double* mom9, double* out6)
+{
+    if (!mom9 || !out6) return RLBM_EINVAL;
+    const Frame fr = landau_frame(mom9);
+    out6[0] = fr.n; out6[1] = fr.eps; out6[2] = fr.Ux; out6[3] = fr.Uy; out6[4] = fr.T; out6[5] = fr.U0;
+    return fr.ok ? RLBM_OK : RLBM_ENONPHYS;
+}
+
+// Device evaluation of the Landau frame of count moment sets (host arrays
+// mom[count][9] -> out[count][7] = n, eps, U^x, U^y, T, U^0, ok), through the
+// same device function as the kernels.  Synchronous; allocates scratch.
+int rlbm_device_landau(int count, const double* mom, double* out)
+{
+    if (count < 0 || (count > 0 && (!mom || !out))) return RLBM_EINVAL;
+    if (count == 0) return RLBM_OK;
+    double *dm = nullptr, *dout = nullptr;
+    hipError_t e = hipMalloc(&dm, sizeof(double) * 9 * (size_t)count);
+    if (e == hipSuccess) e = hipMalloc(&dout, sizeof(double) * 7 * (size_t)count);
+    if (e == hipSuccess) e = hipMemcpy(dm, mom, sizeof(double) * 9 * (size_t)count, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_landau_probe(dm, dout, count, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(out, dout, sizeof(double) * 7 * (size_t)count, hipMemcpyDeviceToHost);
+    if (dm) (void)hipFree(dm);
+    if (dout) (void)hipFree(dout);
+    return e == hipSuccess ? RLBM_OK : RLBM_EDEVICE;
+}
+
+}  // extern "C"

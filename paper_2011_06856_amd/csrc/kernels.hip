@@ -1,0 +1,403 @@
+// kernels.hip -- gfx950 kernels of the relativistic lattice Boltzmann step.
+//
+// Layout: populations f[v][y][x] (structure of arrays), one plane per
+// discrete velocity, so that 64 consecutive x sites of a wavefront read and
+// write 64 consecutive elements of a plane.
+//
+// Fused stream-and-collide (Eq. discrete-rbe): a work-group owns a tile of 64
+// consecutive sites of one row (lane = site) and splits the discrete
+// velocities into contiguous chunks, one per wavefront.  Per step:
+//   1. each wave pulls its velocities' bilinear upwind values (Eq.
+//      interpolation) from the 2x2 upwind cell quad, keeps them in registers
+//      and accumulates their moments (Eq. discrete_sum_moments);
+//   2. the per-wave partial moments are reduced through LDS in FP64, and the
+//      Landau frame (n, eps, U) is solved in FP64 per site;
+//   3. the waves compute the truncated equilibrium's harmonic coefficients of
+//      the shells (FP64, stored to LDS in the compute precision);
+//   4. each wave rebuilds f_eq of its velocities from the coefficients,
+//      relaxes (Eq. collision, relaxing sign) and stores to the other buffer.
+// Velocities of a chunk beyond the register budget VPT are streamed twice
+// (recomputed in step 4) instead of being held.
+#include "rlbm_internal.h"
+
+namespace {
+
+// Work-groups are dealt round-robin to the 8 XCDs (block b runs on XCD b % 8);
+// renumber them so that each XCD owns one contiguous range of tiles, whose
+// neighbouring rows then share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7, k = b & 7, j = b >> 3;
+    return k * q + min(k, r) + j;
+}
+
+__device__ __forceinline__ int wrap_idx(int i, int n, int bc)
+{
+    if (bc == RLBM_BC_PERIODIC) {
+        if (i < 0) i += n;
+        if (i >= n) i -= n;
+    } else {
+        i = i < 0 ? 0 : (i >= n ? n - 1 : i);
+    }
+    return i;
+}
+
+template <typename TS, typename TC, int NM, int VPT>
+__global__ __launch_bounds__(1024) void k_stream_collide(const TS* __restrict__ fin, TS* __restrict__ fout,
+                                                         const VelRec<TC>* __restrict__ vel,
+                                                         const double* __restrict__ Gtab,
+                                                         const double* __restrict__ Pc, SCParams P)
+{
+    constexpr int NT = 2 * NM + 1;
+    constexpr int NMOM = sizeof(TC) == 8 ? 9 : 8;   // FP32: T^yy = T^00 - T^xx
+    constexpr int GS = (RLBM_NMAX + 1) * (RLBM_NMAX + 1);
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int NW = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    TC* part = reinterpret_cast<TC*>(smem);            // [NW][NMOM][64]
+    TC* coef = part + NW * NMOM * 64;                   // [Np][NT][64]
+
+    const int ntx = (P.nx + 63) >> 6;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int ty = tile / ntx;
+    const int tx = tile - ty * ntx;
+    const int x = tx * 64 + lane;
+    const bool active = x < P.nx;
+    const int xc = active ? x : P.nx - 1;
+    const int xm = wrap_idx(xc - 1, P.nx, P.bcx), xp = wrap_idx(xc + 1, P.nx, P.bcx);
+    // row offsets (uniform) and column indices (per lane) inside one plane
+    const int row = ty * P.nx;
+    const int rowm = wrap_idx(ty - 1, P.ny, P.bcy) * P.nx;
+    const int rowp = wrap_idx(ty + 1, P.ny, P.bcy) * P.nx;
+    const int v0 = w * P.chunk;
+    const int v1 = min(v0 + P.chunk, P.nvel);
+
+    // per-lane byte offsets inside a row (unsigned 32-bit: base + offset form)
+    const unsigned oc = (unsigned)xc * sizeof(TS), om = (unsigned)xm * sizeof(TS), op = (unsigned)xp * sizeof(TS);
+    auto ld = [](const TS* base, unsigned off) -> TC {
+        return (TC)*reinterpret_cast<const TS*>(reinterpret_cast<const char*>(base) + off);
+    };
+    auto stream = [&](int v) -> TC {
+        const VelRec<TC>& R = vel[v];
+        const TS* fv = fin + (size_t)v * (size_t)P.S;
+        const unsigned os = R.sx > 0 ? om : op;
+        const TS* f0 = fv + row;
+        const TS* f1 = fv + (R.sy > 0 ? rowm : rowp);
+        const TC f00 = ld(f0, oc), f10 = ld(f0, os);
+        const TC f01 = ld(f1, oc), f11 = ld(f1, os);
+        return R.w00 * f00 + R.w10 * f10 + R.w01 * f01 + R.w11 * f11;
+    };
+
+    // 1. stream and accumulate moments.  The unrolled part has no branches
+    // (out-of-chunk slots read a valid plane and contribute zero) and issues
+    // the loads of LB velocities before using them, so that many loads of a
+    // wave are in flight together.
+    constexpr int LB = 8;
+    static_assert(VPT % LB == 0, "VPT must be a multiple of the load batch");
+    TC fs[VPT];
+    TC m[NMOM];
+#pragma unroll
+    for (int j = 0; j < NMOM; ++j) m[j] = TC(0);
+#pragma unroll
+    for (int kb = 0; kb < VPT; kb += LB) {
+        TC raw[LB][4];
+#pragma unroll
+        for (int b = 0; b < LB; ++b) {
+            const int k = kb + b;
+            const int v = (v0 + k < v1) ? v0 + k : P.nvel - 1;
+            const VelRec<TC>& R = vel[v];
+            const TS* fv = fin + (size_t)v * (size_t)P.S;
+            const unsigned os = R.sx > 0 ? om : op;
+            const TS* f0 = fv + row;
+            const TS* f1 = fv + (R.sy > 0 ? rowm : rowp);
+            raw[b][0] = ld(f0, oc);
+            raw[b][1] = ld(f0, os);
+            raw[b][2] = ld(f1, oc);
+            raw[b][3] = ld(f1, os);
+        }
+#pragma unroll
+        for (int b = 0; b < LB; ++b) {
+            const int k = kb + b;
+            const bool valid = v0 + k < v1;
+            const int v = valid ? v0 + k : P.nvel - 1;
+            const VelRec<TC>& R = vel[v];
+            const TC fr = R.w00 * raw[b][0] + R.w10 * raw[b][1] + R.w01 * raw[b][2] + R.w11 * raw[b][3];
+            const TC f = valid ? fr : TC(0);
+            fs[k] = f;
+#pragma unroll
+            for (int j = 0; j < NMOM; ++j) m[j] += R.P[j] * f;
+        }
+    }
+    for (int v = v0 + VPT; v < v1; ++v) {
+        const TC f = stream(v);
+        const VelRec<TC>& R = vel[v];
+#pragma unroll
+        for (int j = 0; j < NMOM; ++j) m[j] += R.P[j] * f;
+    }
+
+    // 2. cross-wave reduction in FP64 and Landau frame
+#pragma unroll
+    for (int j = 0; j < NMOM; ++j) part[(w * NMOM + j) * 64 + lane] = m[j];
+    __syncthreads();
+    double mom[9];
+#pragma unroll
+    for (int j = 0; j < NMOM; ++j) {
+        double s = 0.0;
+        for (int u = 0; u < NW; ++u) s += (double)part[(u * NMOM + j) * 64 + lane];
+        mom[j] = s;
+    }
+    if (NMOM == 8) mom[8] = mom[3] - mom[6];
+    const Frame fr = landau_frame(mom);
+    if (!fr.ok && active) atomicOr(P.flag, 1);
+    // a site without a physical frame is streamed without collision (its
+    // frame may hold NaN, so the rates are zeroed rather than scaled)
+    const TC a0 = fr.ok ? (TC)(P.rate * fr.U0) : TC(0);
+    const TC ax = fr.ok ? (TC)(P.rate * fr.Ux) : TC(0);
+    const TC ay = fr.ok ? (TC)(P.rate * fr.Uy) : TC(0);
+
+    // 3. equilibrium coefficients per shell, shells dealt to waves
+    for (int i = w; i < P.Np; i += NW) {
+        TC* ci = coef + i * NT * 64 + lane;
+        shell_coeffs<NM>(Gtab + (size_t)i * GS, Pc, fr.n, fr.T, fr.U0, fr.Ux, fr.Uy,
+                         [&](int m, double cm, double sm) {
+                             if (!fr.ok) cm = sm = 0.0;
+                             if (m == 0) {
+                                 ci[0] = (TC)cm;
+                             } else {
+                                 ci[(2 * m - 1) * 64] = (TC)cm;
+                                 ci[(2 * m) * 64] = (TC)sm;
+                             }
+                         });
+    }
+    __syncthreads();
+
+    // 4. equilibrium, relaxation, store
+    if (v0 >= v1) return;
+    int shell = v0 / P.K;
+    int next = (shell + 1) * P.K;
+    TC cc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) cc[t] = coef[(shell * NT + t) * 64 + lane];
+    TS* const out_row = fout + row + x;
+    auto collide = [&](int v, TC f) {
+        if (v >= next) {
+            ++shell;
+            next += P.K;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) cc[t] = coef[(shell * NT + t) * 64 + lane];
+        }
+        const VelRec<TC>& R = vel[v];
+        TC feq = cc[0] * R.H[0];
+#pragma unroll
+        for (int t = 1; t < NT; ++t) feq += cc[t] * R.H[t];
+        const TC om = a0 - ax * R.cth - ay * R.sth;
+        const TC fn = f + om * (feq - f);
+        if (active) out_row[(size_t)v * (size_t)P.S] = (TS)fn;
+    };
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        const int v = v0 + k;
+        if (v < v1) collide(v, fs[k]);
+    }
+    for (int v = v0 + VPT; v < v1; ++v) collide(v, stream(v));
+}
+
+// Initial populations: the truncated equilibrium of given fields, one thread
+// per site.  fields = [n | T | U^x | U^y], each S doubles.
+template <typename TS, int NM>
+__global__ __launch_bounds__(256) void k_init(const double* __restrict__ fields, TS* __restrict__ f,
+                                              const VelRec<double>* __restrict__ vel, const double* __restrict__ G,
+                                              const double* __restrict__ Pc, long long S, int K, int Np)
+{
+    constexpr int NT = 2 * NM + 1;
+    constexpr int GS = (RLBM_NMAX + 1) * (RLBM_NMAX + 1);
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    const double n = fields[s], T = fields[S + s], ux = fields[2 * S + s], uy = fields[3 * S + s];
+    const double U0 = sqrt(1.0 + ux * ux + uy * uy);
+    for (int i = 0; i < Np; ++i) {
+        double c[NT];
+        shell_coeffs<NM>(G + (size_t)i * GS, Pc, n, T, U0, ux, uy, [&](int m, double cm, double sm) {
+            if (m == 0) {
+                c[0] = cm;
+            } else {
+                c[2 * m - 1] = cm;
+                c[2 * m] = sm;
+            }
+        });
+        for (int j = 0; j < K; ++j) {
+            const int v = i * K + j;
+            double fe = 0.0;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) fe += c[t] * vel[v].H[t];
+            f[(long long)v * S + s] = (TS)fe;
+        }
+    }
+}
+
+// Macroscopic fields of the stored populations (FP64 moments and Landau
+// frame), one thread per site, plus per-block partial charges.
+template <typename TS>
+__global__ __launch_bounds__(256) void k_fields(const TS* __restrict__ f, const VelRec<double>* __restrict__ vel,
+                                                double* __restrict__ out, double* __restrict__ partials,
+                                                int* flag, long long S, int nvel)
+{
+    __shared__ double red[4][256];
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double m[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (s < S) {
+        for (int v = 0; v < nvel; ++v) {
+            const double fv = (double)f[(long long)v * S + s];
+#pragma unroll
+            for (int j = 0; j < 9; ++j) m[j] += vel[v].P[j] * fv;
+        }
+        const Frame fr = landau_frame(m);
+        const double nan = __builtin_nan("");
+        out[s] = fr.ok ? fr.n : nan;
+        out[S + s] = fr.ok ? fr.eps : nan;
+        out[2 * S + s] = fr.ok ? fr.Ux : nan;
+        out[3 * S + s] = fr.ok ? fr.Uy : nan;
+        if (!fr.ok) atomicOr(flag, 1);
+    }
+    red[0][threadIdx.x] = m[0];
+    red[1][threadIdx.x] = m[3];
+    red[2][threadIdx.x] = m[4];
+    red[3][threadIdx.x] = m[5];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) partials[(size_t)blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+template <typename TS, typename TC, int NM, int VPT>
+hipError_t launch_sc_t(int waves, const SCParams& p, hipStream_t st)
+{
+    constexpr int NT = 2 * NM + 1;
+    constexpr int NMOM = sizeof(TC) == 8 ? 9 : 8;
+    const size_t lds = (size_t)waves * NMOM * 64 * sizeof(TC) + (size_t)p.Np * NT * 64 * sizeof(TC);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    static size_t configured = 0;
+    if (lds > 64 * 1024 && lds > configured) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stream_collide<TS, TC, NM, VPT>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        configured = lds;
+    }
+    const long long tiles = (long long)((p.nx + 63) / 64) * p.ny;
+    if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_stream_collide<TS, TC, NM, VPT>), dim3((unsigned)tiles), dim3(64 * waves), lds, st,
+                       static_cast<const TS*>(p.fin), static_cast<TS*>(p.fout), static_cast<const VelRec<TC>*>(p.vel),
+                       p.G, p.Pc, p);
+    return hipGetLastError();
+}
+
+// Held values per lane, by storage precision and order class: the register
+// budget (128 VGPRs at 16 waves per work-group) is shared with the FP64
+// coefficient evaluation, whose size grows with the order.
+template <typename TC, int NM>
+struct Vpt {
+    static constexpr int value = sizeof(TC) == 8 ? (NM <= 3 ? 32 : (NM <= 5 ? 24 : 16))
+                                                 : (NM <= 3 ? 64 : (NM <= 5 ? 40 : 24));
+};
+
+template <typename TS, typename TC>
+hipError_t launch_sc_n(int nmax, int waves, const SCParams& p, hipStream_t st)
+{
+    switch (nmax) {
+        case 3: return launch_sc_t<TS, TC, 3, Vpt<TC, 3>::value>(waves, p, st);
+        case 5: return launch_sc_t<TS, TC, 5, Vpt<TC, 5>::value>(waves, p, st);
+        case 7: return launch_sc_t<TS, TC, 7, Vpt<TC, 7>::value>(waves, p, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename TS>
+hipError_t launch_init_t(int nmax, const double* fields, void* f, const VelRec<double>* vel, const double* G,
+                         const double* Pc, long long S, int K, int Np, hipStream_t st)
+{
+    const unsigned blocks = (unsigned)((S + 255) / 256);
+    switch (nmax) {
+        case 3: hipLaunchKernelGGL((k_init<TS, 3>), dim3(blocks), dim3(256), 0, st, fields, (TS*)f, vel, G, Pc, S, K, Np); break;
+        case 5: hipLaunchKernelGGL((k_init<TS, 5>), dim3(blocks), dim3(256), 0, st, fields, (TS*)f, vel, G, Pc, S, K, Np); break;
+        case 7: hipLaunchKernelGGL((k_init<TS, 7>), dim3(blocks), dim3(256), 0, st, fields, (TS*)f, vel, G, Pc, S, K, Np); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int max_vpt(int prec, int nmax)
+{
+    if (prec == RLBM_F64) return nmax <= 3 ? Vpt<double, 3>::value : (nmax <= 5 ? Vpt<double, 5>::value : Vpt<double, 7>::value);
+    return nmax <= 3 ? Vpt<float, 3>::value : (nmax <= 5 ? Vpt<float, 5>::value : Vpt<float, 7>::value);
+}
+
+int default_waves(int prec, int nmax, int nvel)
+{
+    const int vpt = max_vpt(prec, nmax);
+    int w = (nvel + vpt - 1) / vpt;
+    return w < 1 ? 1 : (w > 16 ? 16 : w);
+}
+
+int fields_blocks(long long S) { return (int)((S + 255) / 256); }
+
+hipError_t launch_init(int prec, int nmax, const double* fields, void* f, const VelRec<double>* vel, const double* G,
+                       const double* Pc, int nx, int ny, int nvel, int K, int Np, hipStream_t st)
+{
+    (void)nvel;
+    const long long S = (long long)nx * ny;
+    if (prec == RLBM_F64) return launch_init_t<double>(nmax, fields, f, vel, G, Pc, S, K, Np, st);
+    if (prec == RLBM_F32) return launch_init_t<float>(nmax, fields, f, vel, G, Pc, S, K, Np, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_stream_collide(int prec, int nmax, int waves, const SCParams& p, hipStream_t st)
+{
+    if (waves < 1 || waves > 16) return hipErrorInvalidValue;
+    if (prec == RLBM_F64) return launch_sc_n<double, double>(nmax, waves, p, st);
+    if (prec == RLBM_F32) return launch_sc_n<float, float>(nmax, waves, p, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fields(int prec, const void* f, const VelRec<double>* vel, double* out, double* partials, int* flag,
+                         int nx, int ny, int nvel, hipStream_t st)
+{
+    const long long S = (long long)nx * ny;
+    const unsigned blocks = (unsigned)fields_blocks(S);
+    if (prec == RLBM_F64)
+        hipLaunchKernelGGL((k_fields<double>), dim3(blocks), dim3(256), 0, st, (const double*)f, vel, out, partials, flag, S, nvel);
+    else if (prec == RLBM_F32)
+        hipLaunchKernelGGL((k_fields<float>), dim3(blocks), dim3(256), 0, st, (const float*)f, vel, out, partials, flag, S, nvel);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+namespace {
+__global__ void k_landau_probe(const double* __restrict__ mom, double* __restrict__ out, int count)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    double m[9];
+    for (int j = 0; j < 9; ++j) m[j] = mom[9 * i + j];
+    const Frame fr = landau_frame(m);
+    out[7 * i + 0] = fr.n;
+    out[7 * i + 1] = fr.eps;
+    out[7 * i + 2] = fr.Ux;
+    out[7 * i + 3] = fr.Uy;
+    out[7 * i + 4] = fr.T;
+    out[7 * i + 5] = fr.U0;
+    out[7 * i + 6] = fr.ok;
+}
+}  // namespace
+
+hipError_t launch_landau_probe(const double* mom, double* out, int count, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_landau_probe, dim3((count + 63) / 64), dim3(64), 0, st, mom, out, count);
+    return hipGetLastError();
+}

@@ -1,0 +1,170 @@
+// rlbm_internal.h -- shared definitions of the HIP library (not installed).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "../../include/rlbm.h"
+
+// Largest supported expansion order N and the stride of the harmonic tables.
+#define RLBM_NMAX 7
+#define RLBM_NT (2 * RLBM_NMAX + 1)
+
+// Per-velocity constants of the fused kernel, read with wave-uniform indices
+// (scalar loads).  32 entries of T:
+//   w00 w10 w01 w11  bilinear weights of the cells (x,y) (x-sx,y) (x,y-sy)
+//                    (x-sx,y-sy): (1-ax)(1-ay), ax(1-ay), (1-ax)ay, ax ay with
+//                    ax = dt|cos|, ay = dt|sin| (Eq. interpolation)
+//   P[9]             p, p c, p s, p^2, p^2 c, p^2 s, p^2 c^2, p^2 c s, p^2 s^2
+//                    (Eq. discrete_sum_moments rows)
+//   cth sth          direction n_v (collision frequency U^0 - U.n_v)
+//   sx sy            upwind signs sgn(cos), sgn(sin) (sgn 0 = +1) as +-1
+//   H[15]            w_v {1, cos th, sin th, cos 2th, sin 2th, ...}: the
+//                    equilibrium is f_eq_v = sum_t coef_shell(v)[t] H[t]
+template <typename T>
+struct alignas(16) VelRec {
+    T w00, w10, w01, w11;
+    T P[9];
+    T cth, sth;
+    T sx, sy;
+    T H[RLBM_NT];
+};
+static_assert(sizeof(VelRec<float>) == 32 * 4, "VelRec layout");
+
+// Host-side quadrature and coefficient tables (FP64).
+struct HostQuad {
+    int Np = 0, K = 0, N = 0, nvel = 0, rotate = 1;
+    std::vector<double> shell_p, shell_w;          // [Np]
+    std::vector<double> p, theta, w, cth, sth;     // [nvel]
+    // G[i][m][r]: equilibrium harmonic m of shell i is
+    //   z^m sum_r G[i][m][r] n T^{m+r-1} P_{m+r,m}(U^0),  z = U^x + i U^y
+    std::vector<double> G;                         // [Np][NMAX+1][NMAX+1]
+    // Pc[m][r][l]: P_{m+r,m}(u) = sum_l Pc[m][r][l] u^{r-2l} (Horner from l = 0)
+    std::vector<double> Pc;                        // [NMAX+1][NMAX+1][NMAX/2+1]
+};
+
+#define RLBM_PC_L (RLBM_NMAX / 2 + 1)
+
+int build_host_quad(HostQuad& q, int Np, int K, int N, int rotate, std::string& err);
+void build_vel_table(const HostQuad& q, double dt, std::vector<VelRec<double>>& vd);
+
+// ---------------------------------------------------------------------------
+// Device/host numerics shared by the kernels and the host debug entry points.
+// ---------------------------------------------------------------------------
+
+// Finite test usable on host and device.  (x - x == 0 is not: with FMA
+// contraction x - x for x = a*b becomes fma(a, b, -x), the rounding error.)
+__host__ __device__ inline bool finite_d(double x) { return __builtin_isfinite(x); }
+
+struct Frame {
+    double n, eps, U0, Ux, Uy, T;
+    int ok;
+};
+
+// Landau frame of the nine moments m = (N0, Nx, Ny, T00, T0x, T0y, Txx, Txy,
+// Tyy): eps = largest root of det(T^{mu nu} - lambda eta^{mu nu}) by Newton
+// from the right (monotone on the concave branch beyond the largest root),
+// then the boost beta from the two spatial rows of (T - eps eta) u = 0 with
+// u_0 = 1, U = gamma (1, beta), n = U_mu N^mu, T = eps / (2n).
+__host__ __device__ inline Frame landau_frame(const double* m)
+{
+    const double a = m[3], b = m[4], c = m[5], d = m[6], e = m[7], f = m[8];
+    const double c2 = a - d - f;
+    const double c1 = a * (d + f) - d * f + e * e - b * b - c * c;
+    auto pv = [&](double l) {
+        return (a - l) * ((d + l) * (f + l) - e * e) - b * (b * (f + l) - e * c) + c * (b * e - (d + l) * c);
+    };
+    auto dp = [&](double l) { return (-3.0 * l + 2.0 * c2) * l + c1; };
+    double lam = a;
+    if (!(pv(lam) <= 0.0 && dp(lam) < 0.0 && (-6.0 * lam + 2.0 * c2) < 0.0)) {
+        const double g0 = a + fabs(b) + fabs(c);
+        const double g1 = -d + fabs(b) + fabs(e);
+        const double g2 = -f + fabs(c) + fabs(e);
+        lam = fmax(g0, fmax(g1, g2));
+    }
+    for (int it = 0; it < 100; ++it) {
+        const double step = pv(lam) / dp(lam);
+        if (!(step > 0.0)) break;
+        lam -= step;
+        if (step <= 2.0e-16 * fabs(lam)) break;
+    }
+    Frame fr;
+    const double eps = lam;
+    const double A = d + eps, B = e, C = f + eps;
+    const double det = A * C - B * B;
+    const double bx = (b * C - B * c) / det;
+    const double by = (A * c - B * b) / det;
+    const double b2 = bx * bx + by * by;
+    const double g = 1.0 / sqrt(1.0 - b2);
+    fr.eps = eps;
+    fr.U0 = g;
+    fr.Ux = g * bx;
+    fr.Uy = g * by;
+    fr.n = g * (m[0] - bx * m[1] - by * m[2]);
+    fr.T = eps / (2.0 * fr.n);
+    fr.ok = (det > 0.0) && (b2 < 1.0) && (fr.n > 0.0) && (eps > 0.0) && finite_d(fr.n) && finite_d(fr.T) &&
+            finite_d(fr.Ux) && finite_d(fr.Uy);
+    return fr;
+}
+
+// Harmonic coefficients of the truncated equilibrium on one shell,
+//   f_eq / w = sum_m C_m cos(m th) + S_m sin(m th),
+// handed to emit(m, C_m, S_m) one harmonic at a time (few live registers).
+// Gs = G[shell] ([NMAX+1][NMAX+1]), zero beyond the expansion order, so that
+// harmonics above the order come out as zero.
+template <int NM, typename Emit>
+__host__ __device__ inline void shell_coeffs(const double* __restrict__ Gs, const double* __restrict__ Pc, double n,
+                                             double T, double U0, double Ux, double Uy, Emit emit)
+{
+    const double u2 = U0 * U0;
+    double zr = 1.0, zi = 0.0;   // (U^x + i U^y)^m
+    double nTm = n / T;          // n T^{m-1}
+#pragma unroll
+    for (int m = 0; m <= NM; ++m) {
+        double acc = 0.0, nTk = nTm;
+#pragma unroll
+        for (int r = 0; r + m <= NM; ++r) {
+            // P_{m+r,m}(U^0) by Horner in (U^0)^2
+            const double* pc = Pc + (m * (RLBM_NMAX + 1) + r) * RLBM_PC_L;
+            double pk = pc[0];
+#pragma unroll
+            for (int l = 1; 2 * l <= r; ++l) pk = pk * u2 + pc[l];
+            if (r & 1) pk *= U0;
+            acc += Gs[m * (RLBM_NMAX + 1) + r] * nTk * pk;
+            nTk *= T;
+        }
+        emit(m, acc * zr, acc * zi);
+        nTm *= T;
+        const double nzr = zr * Ux - zi * Uy;
+        zi = zr * Uy + zi * Ux;
+        zr = nzr;
+    }
+}
+
+// Kernel launch parameters.
+struct SCParams {
+    const void* fin;
+    void* fout;
+    const void* vel;       // VelRec<TC>[nvel]
+    const double* G;       // [Np][NMAX+1][NMAX+1]
+    const double* Pc;
+    int nx, ny, nvel, K, Np, N;
+    int bcx, bcy;
+    long long S;
+    double rate;           // dt / tau (0 for tau = inf)
+    int* flag;
+    int chunk;             // velocities per wave
+};
+
+// Launchers (kernels.hip).
+hipError_t launch_init(int prec, int nmax, const double* fields, void* f, const VelRec<double>* vel, const double* G,
+                       const double* Pc, int nx, int ny, int nvel, int K, int Np, hipStream_t st);
+hipError_t launch_stream_collide(int prec, int nmax, int waves, const SCParams& p, hipStream_t st);
+hipError_t launch_fields(int prec, const void* f, const VelRec<double>* vel, double* out, double* partials,
+                         int* flag, int nx, int ny, int nvel, hipStream_t st);
+hipError_t launch_landau_probe(const double* mom, double* out, int count, hipStream_t st);
+int default_waves(int prec, int nmax, int nvel);
+int max_vpt(int prec, int nmax);
+int fields_blocks(long long S);

@@ -1,0 +1,219 @@
+"""Python binding of librlbm.so (include/rlbm.h): argument marshalling only.
+
+Every step of the method runs in the library's HIP kernels.  PyTorch supplies
+device memory (the workspace tensor) and the stream.  If the shared library is
+missing the import of this module fails; there is no fallback.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(_HERE, "librlbm.so")
+
+RLBM_OK, RLBM_EINVAL, RLBM_ENOMEM, RLBM_EDEVICE, RLBM_ENONPHYS, RLBM_ESTATE = 0, -1, -2, -3, -4, -5
+RLBM_F64, RLBM_F32, RLBM_BF16DEV = 0, 1, 2
+RLBM_BC_PERIODIC, RLBM_BC_CLAMP = 0, 1
+PRECISIONS = {"f64": RLBM_F64, "f32": RLBM_F32, "bf16dev": RLBM_BF16DEV}
+ELEM_BYTES = {RLBM_F64: 8, RLBM_F32: 4, RLBM_BF16DEV: 2}
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+_L = None
+
+# (name, restype, argtypes) of every exported entry point of include/rlbm.h
+SIGNATURES = [
+    ("rlbm_init_quadrature", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    ("rlbm_nvel", ctypes.c_int, [_vp]),
+    ("rlbm_get_quadrature", ctypes.c_int, [_vp, _dp, _dp, _dp]),
+    ("rlbm_workspace_bytes", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    ("rlbm_init_fields", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp]),
+    ("rlbm_step", ctypes.c_int, [_vp, ctypes.c_int]),
+    ("rlbm_step_timed", ctypes.c_int, [_vp, ctypes.c_int, _dp]),
+    ("rlbm_moments", ctypes.c_int, [_vp, _dp, _dp, _dp, _dp, _dp]),
+    ("rlbm_populations_bytes", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    ("rlbm_get_populations", ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
+    ("rlbm_set_populations", ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
+    ("rlbm_set_waves", ctypes.c_int, [_vp, ctypes.c_int]),
+    ("rlbm_get_waves", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
+    ("rlbm_host_feq", ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]),
+    ("rlbm_host_landau", ctypes.c_int, [_dp, _dp]),
+    ("rlbm_device_landau", ctypes.c_int, [ctypes.c_int, _dp, _dp]),
+    ("rlbm_last_error", ctypes.c_char_p, [_vp]),
+    ("rlbm_destroy", ctypes.c_int, [_vp]),
+]
+
+
+class RlbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("rlbm error %d: %s" % (code, msg))
+        self.code = code
+
+
+class NonPhysicalState(RlbmError):
+    pass
+
+
+def lib():
+    """Load librlbm.so (built in-tree by paper_2011_06856_amd.build)."""
+    global _L
+    if _L is None:
+        # torch ships its own libamdhip64.so.7; load it (and initialise it)
+        # first so that librlbm.so binds to the same HIP runtime by soname.
+        try:
+            import torch
+            torch.cuda.is_available()
+        except ImportError:
+            pass
+        if not os.path.exists(SO_PATH):
+            raise ImportError("librlbm.so is not built: run `python -m paper_2011_06856_amd.build` "
+                              "(or __graft_entry__.build()) first")
+        L = ctypes.CDLL(SO_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype, fn.argtypes = res, args
+        _L = L
+    return _L
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def _arr(a, shape):
+    if a is None:
+        return None
+    return np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), shape))
+
+
+def host_landau(mom9):
+    """Landau frame of nine moments with the library's host code (no GPU):
+    (n, eps, U^x, U^y, T, U^0), ok."""
+    m = np.ascontiguousarray(mom9, dtype=np.float64)
+    out = np.zeros(6)
+    rc = lib().rlbm_host_landau(_p(m), _p(out))
+    return out, rc == RLBM_OK
+
+
+def device_landau(moms):
+    """Landau frames of moment sets (count, 9) on the GPU: (count, 7) with
+    columns n, eps, U^x, U^y, T, U^0, ok."""
+    m = np.ascontiguousarray(moms, dtype=np.float64).reshape(-1, 9)
+    out = np.zeros((m.shape[0], 7))
+    rc = lib().rlbm_device_landau(m.shape[0], _p(m), _p(out))
+    if rc != RLBM_OK:
+        raise RlbmError(rc, "device_landau failed")
+    return out
+
+
+class Solver:
+    """One simulation context (rlbm_ctx)."""
+
+    def __init__(self, n_radial, n_angle, order=None, rotate=True):
+        order = n_radial - 1 if order is None else order
+        h = _vp()
+        rc = lib().rlbm_init_quadrature(ctypes.byref(h), int(n_radial), int(n_angle), int(order), 1 if rotate else 0)
+        if rc != RLBM_OK:
+            raise RlbmError(rc, "invalid quadrature (Np=%d, K=%d, N=%d)" % (n_radial, n_angle, order))
+        self._h = h
+        self.Np, self.K, self.N = int(n_radial), int(n_angle), int(order)
+        self.nvel = lib().rlbm_nvel(h)
+        self.workspace = None
+        self.nx = self.ny = 0
+        self.precision = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().rlbm_destroy(h)
+            self._h = None
+
+    def _check(self, rc):
+        if rc == RLBM_OK:
+            return
+        msg = lib().rlbm_last_error(self._h).decode()
+        if rc == RLBM_ENONPHYS:
+            raise NonPhysicalState(rc, msg)
+        raise RlbmError(rc, msg)
+
+    def quadrature(self):
+        p, th, w = (np.zeros(self.nvel) for _ in range(3))
+        self._check(lib().rlbm_get_quadrature(self._h, _p(p), _p(th), _p(w)))
+        return p, th, w
+
+    def host_feq(self, n, T, ux=0.0, uy=0.0):
+        out = np.zeros(self.nvel)
+        self._check(lib().rlbm_host_feq(self._h, n, T, ux, uy, _p(out)))
+        return out
+
+    def workspace_bytes(self, nx, ny, precision="f32"):
+        b = ctypes.c_size_t()
+        self._check(lib().rlbm_workspace_bytes(self._h, nx, ny, PRECISIONS[precision], ctypes.byref(b)))
+        return b.value
+
+    def init_fields(self, nx, ny, n, T, ux=None, uy=None, tau=math.inf, dt=1.0, bcx=0, bcy=0,
+                    precision="f32", device=None, stream=None, workspace=None):
+        """Fields are (ny, nx) host arrays.  The workspace is a torch uint8
+        tensor on the GPU unless given."""
+        import torch
+        prec = PRECISIONS[precision]
+        shape = (ny, nx)
+        n, T, ux, uy = _arr(n, shape), _arr(T, shape), _arr(ux, shape), _arr(uy, shape)
+        if workspace is None:
+            nbytes = self.workspace_bytes(nx, ny, precision)
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=device or "cuda")
+        if stream is None:
+            stream = torch.cuda.current_stream(workspace.device)
+        self.workspace, self.stream = workspace, stream
+        self._keep = (n, T, ux, uy)
+        self._check(lib().rlbm_init_fields(self._h, nx, ny, _p(n), _p(T), _p(ux), _p(uy), float(tau), float(dt),
+                                           int(bcx), int(bcy), prec, _vp(workspace.data_ptr()),
+                                           _vp(stream.cuda_stream)))
+        self.nx, self.ny, self.precision = nx, ny, prec
+        return self
+
+    def step(self, nsteps=1):
+        self._check(lib().rlbm_step(self._h, int(nsteps)))
+
+    def step_timed(self, nsteps):
+        ms = ctypes.c_double()
+        self._check(lib().rlbm_step_timed(self._h, int(nsteps), ctypes.byref(ms)))
+        return ms.value
+
+    def moments(self, raise_nonphysical=True):
+        """n, eps, U^x, U^y as (ny, nx) arrays and the four global charges."""
+        shape = (self.ny, self.nx)
+        n, eps, ux, uy = (np.empty(shape) for _ in range(4))
+        ch = np.zeros(4)
+        rc = lib().rlbm_moments(self._h, _p(n), _p(eps), _p(ux), _p(uy), _p(ch))
+        if rc != RLBM_ENONPHYS or raise_nonphysical:
+            self._check(rc)
+        return n, eps, ux, uy, ch
+
+    def populations_bytes(self):
+        b = ctypes.c_size_t()
+        self._check(lib().rlbm_populations_bytes(self._h, ctypes.byref(b)))
+        return b.value
+
+    def get_populations(self):
+        dt = {RLBM_F64: np.float64, RLBM_F32: np.float32, RLBM_BF16DEV: np.uint8}[self.precision]
+        buf = np.empty(self.populations_bytes() // np.dtype(dt).itemsize, dtype=dt)
+        self._check(lib().rlbm_get_populations(self._h, _vp(buf.ctypes.data), buf.nbytes))
+        if self.precision == RLBM_BF16DEV:
+            return buf
+        return buf.reshape(self.nvel, self.ny, self.nx)
+
+    def set_populations(self, f):
+        f = np.ascontiguousarray(f)
+        self._check(lib().rlbm_set_populations(self._h, _vp(f.ctypes.data), f.nbytes))
+
+    def set_waves(self, waves):
+        self._check(lib().rlbm_set_waves(self._h, int(waves)))
+
+    def get_waves(self):
+        w = ctypes.c_int()
+        self._check(lib().rlbm_get_waves(self._h, ctypes.byref(w)))
+        return w.value
