@@ -22,8 +22,9 @@ struct rlbm_ctx_s {
     double* d_fields = nullptr;
     double* d_partials = nullptr;
     int* d_flag = nullptr;
-    void* d_vel = nullptr;               // VelRec<TC>
-    VelRec<double>* d_veld = nullptr;    // FP64 table for init and fields
+    void* d_vel = nullptr;               // VelRec<TC>[nvel + RLBM_VPAD]
+    VelMeta* d_meta = nullptr;           // [nvel + RLBM_VPAD]
+    VelRec<double>* d_veld = nullptr;    // FP64 table for init and fields [nvel]
     double* d_G = nullptr;
     double* d_Pc = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -54,7 +55,8 @@ struct Layout {
 Layout layout(int nvel, long long S, int prec)
 {
     Layout L;
-    const size_t fb = align256((size_t)nvel * S * elem_size(prec));
+    // nvel planes plus one spare plane written by the null table entries
+    const size_t fb = align256((size_t)(nvel + 1) * S * elem_size(prec));
     L.f0 = 0;
     L.f1 = L.f0 + fb;
     L.fields = L.f1 + fb;
@@ -69,10 +71,11 @@ int nmax_of(int N) { return N <= 3 ? 3 : (N <= 5 ? 5 : 7); }
 void free_tables(rlbm_ctx c)
 {
     if (c->d_vel) (void)hipFree(c->d_vel);
+    if (c->d_meta) (void)hipFree(c->d_meta);
     if (c->d_veld) (void)hipFree(c->d_veld);
     if (c->d_G) (void)hipFree(c->d_G);
     if (c->d_Pc) (void)hipFree(c->d_Pc);
-    c->d_vel = nullptr; c->d_veld = nullptr; c->d_G = nullptr; c->d_Pc = nullptr;
+    c->d_vel = nullptr; c->d_meta = nullptr; c->d_veld = nullptr; c->d_G = nullptr; c->d_Pc = nullptr;
 }
 
 bool finite_arr(const double* a, long long S)
@@ -190,22 +193,41 @@ int rlbm_init_fields(rlbm_ctx c, int nx, int ny, const double* n, const double* 
         return hip_fail(c, e, "table upload");
     if ((e = hipMemcpy(c->d_Pc, c->q.Pc.data(), c->q.Pc.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(c, e, "table upload");
+    // kernel tables, padded with null entries (zero weights, spare plane)
+    const size_t npad = nv + RLBM_VPAD;
+    std::vector<VelRec<double>> vpad(npad, VelRec<double>{});
+    for (size_t v = 0; v < nv; ++v) vpad[v] = vd[v];
+    std::vector<VelMeta> meta(npad);
+    const long long es = (long long)elem_size(precision);
+    for (size_t v = 0; v < npad; ++v) {
+        VelMeta& M = meta[v];
+        const bool real = v < nv;
+        M.roff = real ? (long long)v * S * es : 0;
+        M.woff = (long long)(real ? v : nv) * S * es;
+        M.dx = real ? (vd[v].sx > 0 ? -1 : 1) * (int)es : -(int)es;
+        M.sy = real ? (vd[v].sy > 0 ? 1 : -1) : 1;
+        M.shell = real ? (int)(v / c->q.K) : c->q.Np - 1;
+        M.pad = 0;
+    }
+    if ((e = hipMalloc(&c->d_meta, npad * sizeof(VelMeta))) != hipSuccess) return fail(c, RLBM_ENOMEM, "table alloc");
+    if ((e = hipMemcpy(c->d_meta, meta.data(), npad * sizeof(VelMeta), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(c, e, "table upload");
     if (precision == RLBM_F64) {
-        void* p = nullptr;   // the kernel's own copy, so that each table has one owner
-        if ((e = hipMalloc(&p, nv * sizeof(VelRec<double>))) != hipSuccess) return fail(c, RLBM_ENOMEM, "table alloc");
-        if ((e = hipMemcpy(p, vd.data(), nv * sizeof(VelRec<double>), hipMemcpyHostToDevice)) != hipSuccess)
+        void* p = nullptr;
+        if ((e = hipMalloc(&p, npad * sizeof(VelRec<double>))) != hipSuccess) return fail(c, RLBM_ENOMEM, "table alloc");
+        if ((e = hipMemcpy(p, vpad.data(), npad * sizeof(VelRec<double>), hipMemcpyHostToDevice)) != hipSuccess)
             return hip_fail(c, e, "table upload");
         c->d_vel = p;
     } else {
-        std::vector<VelRec<float>> vf(nv);
-        for (size_t v = 0; v < nv; ++v) {
-            const double* s = reinterpret_cast<const double*>(&vd[v]);
-            float* d = reinterpret_cast<float*>(&vf[v]);
-            for (int k = 0; k < 32; ++k) d[k] = (float)s[k];
+        std::vector<VelRec<float>> vf(npad);
+        for (size_t v = 0; v < npad; ++v) {
+            const double* src = reinterpret_cast<const double*>(&vpad[v]);
+            float* dst = reinterpret_cast<float*>(&vf[v]);
+            for (int k = 0; k < 32; ++k) dst[k] = (float)src[k];
         }
         void* p = nullptr;
-        if ((e = hipMalloc(&p, nv * sizeof(VelRec<float>))) != hipSuccess) return fail(c, RLBM_ENOMEM, "table alloc");
-        if ((e = hipMemcpy(p, vf.data(), nv * sizeof(VelRec<float>), hipMemcpyHostToDevice)) != hipSuccess)
+        if ((e = hipMalloc(&p, npad * sizeof(VelRec<float>))) != hipSuccess) return fail(c, RLBM_ENOMEM, "table alloc");
+        if ((e = hipMemcpy(p, vf.data(), npad * sizeof(VelRec<float>), hipMemcpyHostToDevice)) != hipSuccess)
             return hip_fail(c, e, "table upload");
         c->d_vel = p;
     }
@@ -219,6 +241,11 @@ int rlbm_init_fields(rlbm_ctx c, int nx, int ny, const double* n, const double* 
     if ((e = hipMemcpyAsync(c->d_fields, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st)) != hipSuccess)
         return hip_fail(c, e, "field upload");
     if ((e = hipMemsetAsync(c->d_flag, 0, sizeof(int), st)) != hipSuccess) return hip_fail(c, e, "flag clear");
+    for (int b = 0; b < 2; ++b) {   // spare planes written by the null table entries
+        char* spare = static_cast<char*>(c->f[b]) + (size_t)c->q.nvel * S * elem_size(precision);
+        if ((e = hipMemsetAsync(spare, 0, (size_t)S * elem_size(precision), st)) != hipSuccess)
+            return hip_fail(c, e, "spare clear");
+    }
     e = launch_init(precision, nmax_of(c->q.N), c->d_fields, c->f[0], c->d_veld, c->d_G, c->d_Pc, nx, ny,
                     c->q.nvel, c->q.K, c->q.Np, st);
     if (e != hipSuccess) return hip_fail(c, e, "init kernel");
@@ -254,11 +281,13 @@ int rlbm_step(rlbm_ctx c, int nsteps)
     const int waves = c->waves ? c->waves : default_waves(c->prec, nmax_of(c->q.N), c->q.nvel);
     SCParams p;
     p.vel = c->d_vel;
+    p.meta = c->d_meta;
     p.G = c->d_G;
     p.Pc = c->d_Pc;
     p.nx = c->nx; p.ny = c->ny; p.nvel = c->q.nvel; p.K = c->q.K; p.Np = c->q.Np; p.N = c->q.N;
     p.bcx = c->bcx; p.bcy = c->bcy; p.S = c->S; p.rate = c->rate; p.flag = c->d_flag;
-    p.chunk = (c->q.nvel + waves - 1) / waves;
+    const int chunk = (c->q.nvel + waves - 1) / waves;
+    p.chunk = (chunk + RLBM_LB - 1) / RLBM_LB * RLBM_LB;
     for (int s = 0; s < nsteps; ++s) {
         p.fin = c->f[c->cur];
         p.fout = c->f[c->cur ^ 1];

@@ -18,6 +18,8 @@
 //      relaxes (Eq. collision, relaxing sign) and stores to the other buffer.
 // Velocities of a chunk beyond the register budget VPT are streamed twice
 // (recomputed in step 4) instead of being held.
+#include <type_traits>
+
 #include "rlbm_internal.h"
 
 namespace {
@@ -45,12 +47,15 @@ __device__ __forceinline__ int wrap_idx(int i, int n, int bc)
 template <typename TS, typename TC, int NM, int VPT>
 __global__ __launch_bounds__(1024) void k_stream_collide(const TS* __restrict__ fin, TS* __restrict__ fout,
                                                          const VelRec<TC>* __restrict__ vel,
+                                                         const VelMeta* __restrict__ meta,
                                                          const double* __restrict__ Gtab,
                                                          const double* __restrict__ Pc, SCParams P)
 {
     constexpr int NT = 2 * NM + 1;
     constexpr int NMOM = sizeof(TC) == 8 ? 9 : 8;   // FP32: T^yy = T^00 - T^xx
     constexpr int GS = (RLBM_NMAX + 1) * (RLBM_NMAX + 1);
+    constexpr int LB = RLBM_LB;
+    static_assert(VPT % LB == 0, "VPT must be a multiple of the load batch");
     extern __shared__ __align__(16) unsigned char smem[];
     const int NW = blockDim.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -65,76 +70,75 @@ __global__ __launch_bounds__(1024) void k_stream_collide(const TS* __restrict__ 
     const int x = tx * 64 + lane;
     const bool active = x < P.nx;
     const int xc = active ? x : P.nx - 1;
-    const int xm = wrap_idx(xc - 1, P.nx, P.bcx), xp = wrap_idx(xc + 1, P.nx, P.bcx);
-    // row offsets (uniform) and column indices (per lane) inside one plane
-    const int row = ty * P.nx;
-    const int rowm = wrap_idx(ty - 1, P.ny, P.bcy) * P.nx;
-    const int rowp = wrap_idx(ty + 1, P.ny, P.bcy) * P.nx;
+    // Interior tiles (all 64 columns and both x neighbours inside the grid)
+    // reach the x neighbour by a scalar shift of the row base; edge tiles
+    // select a wrapped or clamped column per lane.
+    const bool interior = tx > 0 && (tx + 1) * 64 < P.nx;
+    constexpr unsigned ES = sizeof(TS);
+    const unsigned ocb = (unsigned)xc * ES;
+    const unsigned omb = (unsigned)wrap_idx(xc - 1, P.nx, P.bcx) * ES;
+    const unsigned opb = (unsigned)wrap_idx(xc + 1, P.nx, P.bcx) * ES;
+    const long long rowb = (long long)ty * P.nx * ES;
+    const long long dmb = (long long)wrap_idx(ty - 1, P.ny, P.bcy) * P.nx * ES - rowb;
+    const long long dpb = (long long)wrap_idx(ty + 1, P.ny, P.bcy) * P.nx * ES - rowb;
+    const char* const inb = reinterpret_cast<const char*>(fin) + rowb;
+    char* const outb = reinterpret_cast<char*>(fout) + rowb;
     const int v0 = w * P.chunk;
-    const int v1 = min(v0 + P.chunk, P.nvel);
+    const int nbatch = min(P.chunk, VPT) / LB;   // batches held in registers
 
-    // per-lane byte offsets inside a row (unsigned 32-bit: base + offset form)
-    const unsigned oc = (unsigned)xc * sizeof(TS), om = (unsigned)xm * sizeof(TS), op = (unsigned)xp * sizeof(TS);
-    auto ld = [](const TS* base, unsigned off) -> TC {
-        return (TC)*reinterpret_cast<const TS*>(reinterpret_cast<const char*>(base) + off);
+    auto ld = [](const char* base, unsigned off) -> TC { return (TC)*reinterpret_cast<const TS*>(base + off); };
+    auto load4 = [&](auto fast, int v, TC* r) {
+        const VelMeta& M = meta[v];
+        const char* p0 = inb + M.roff;
+        const char* p1 = p0 + (M.sy > 0 ? dmb : dpb);
+        if (decltype(fast)::value) {
+            r[0] = ld(p0, ocb); r[1] = ld(p0 + M.dx, ocb); r[2] = ld(p1, ocb); r[3] = ld(p1 + M.dx, ocb);
+        } else {
+            const unsigned osb = M.dx < 0 ? omb : opb;
+            r[0] = ld(p0, ocb); r[1] = ld(p0, osb); r[2] = ld(p1, ocb); r[3] = ld(p1, osb);
+        }
     };
-    auto stream = [&](int v) -> TC {
+    auto bilin = [&](int v, const TC* r) -> TC {
         const VelRec<TC>& R = vel[v];
-        const TS* fv = fin + (size_t)v * (size_t)P.S;
-        const unsigned os = R.sx > 0 ? om : op;
-        const TS* f0 = fv + row;
-        const TS* f1 = fv + (R.sy > 0 ? rowm : rowp);
-        const TC f00 = ld(f0, oc), f10 = ld(f0, os);
-        const TC f01 = ld(f1, oc), f11 = ld(f1, os);
-        return R.w00 * f00 + R.w10 * f10 + R.w01 * f01 + R.w11 * f11;
+        return R.w00 * r[0] + R.w10 * r[1] + R.w01 * r[2] + R.w11 * r[3];
     };
 
-    // 1. stream and accumulate moments.  The unrolled part has no branches
-    // (out-of-chunk slots read a valid plane and contribute zero) and issues
-    // the loads of LB velocities before using them, so that many loads of a
-    // wave are in flight together.
-    constexpr int LB = 8;
-    static_assert(VPT % LB == 0, "VPT must be a multiple of the load batch");
+    // 1. stream and accumulate moments, LB velocities' loads in flight at once
     TC fs[VPT];
     TC m[NMOM];
 #pragma unroll
     for (int j = 0; j < NMOM; ++j) m[j] = TC(0);
+    auto phase1 = [&](auto fast) {
 #pragma unroll
-    for (int kb = 0; kb < VPT; kb += LB) {
-        TC raw[LB][4];
+        for (int kb = 0; kb < VPT / LB; ++kb) {
+            if (kb < nbatch) {
+                TC raw[LB][4];
 #pragma unroll
-        for (int b = 0; b < LB; ++b) {
-            const int k = kb + b;
-            const int v = (v0 + k < v1) ? v0 + k : P.nvel - 1;
-            const VelRec<TC>& R = vel[v];
-            const TS* fv = fin + (size_t)v * (size_t)P.S;
-            const unsigned os = R.sx > 0 ? om : op;
-            const TS* f0 = fv + row;
-            const TS* f1 = fv + (R.sy > 0 ? rowm : rowp);
-            raw[b][0] = ld(f0, oc);
-            raw[b][1] = ld(f0, os);
-            raw[b][2] = ld(f1, oc);
-            raw[b][3] = ld(f1, os);
+                for (int b = 0; b < LB; ++b) load4(fast, v0 + kb * LB + b, raw[b]);
+#pragma unroll
+                for (int b = 0; b < LB; ++b) {
+                    const int v = v0 + kb * LB + b;
+                    const TC f = bilin(v, raw[b]);
+                    fs[kb * LB + b] = f;
+                    const VelRec<TC>& R = vel[v];
+#pragma unroll
+                    for (int j = 0; j < NMOM; ++j) m[j] += R.P[j] * f;
+                }
+            }
         }
-#pragma unroll
-        for (int b = 0; b < LB; ++b) {
-            const int k = kb + b;
-            const bool valid = v0 + k < v1;
-            const int v = valid ? v0 + k : P.nvel - 1;
+        for (int v = v0 + VPT; v < v0 + P.chunk; ++v) {
+            TC r[4];
+            load4(fast, v, r);
+            const TC f = bilin(v, r);
             const VelRec<TC>& R = vel[v];
-            const TC fr = R.w00 * raw[b][0] + R.w10 * raw[b][1] + R.w01 * raw[b][2] + R.w11 * raw[b][3];
-            const TC f = valid ? fr : TC(0);
-            fs[k] = f;
 #pragma unroll
             for (int j = 0; j < NMOM; ++j) m[j] += R.P[j] * f;
         }
-    }
-    for (int v = v0 + VPT; v < v1; ++v) {
-        const TC f = stream(v);
-        const VelRec<TC>& R = vel[v];
-#pragma unroll
-        for (int j = 0; j < NMOM; ++j) m[j] += R.P[j] * f;
-    }
+    };
+    if (interior)
+        phase1(std::true_type{});
+    else
+        phase1(std::false_type{});
 
     // 2. cross-wave reduction in FP64 and Landau frame
 #pragma unroll
@@ -160,30 +164,27 @@ __global__ __launch_bounds__(1024) void k_stream_collide(const TS* __restrict__ 
     for (int i = w; i < P.Np; i += NW) {
         TC* ci = coef + i * NT * 64 + lane;
         shell_coeffs<NM>(Gtab + (size_t)i * GS, Pc, fr.n, fr.T, fr.U0, fr.Ux, fr.Uy,
-                         [&](int m, double cm, double sm) {
+                         [&](int mm, double cm, double sm) {
                              if (!fr.ok) cm = sm = 0.0;
-                             if (m == 0) {
+                             if (mm == 0) {
                                  ci[0] = (TC)cm;
                              } else {
-                                 ci[(2 * m - 1) * 64] = (TC)cm;
-                                 ci[(2 * m) * 64] = (TC)sm;
+                                 ci[(2 * mm - 1) * 64] = (TC)cm;
+                                 ci[(2 * mm) * 64] = (TC)sm;
                              }
                          });
     }
     __syncthreads();
 
-    // 4. equilibrium, relaxation, store
-    if (v0 >= v1) return;
-    int shell = v0 / P.K;
-    int next = (shell + 1) * P.K;
+    // 4. equilibrium, relaxation, store (null table entries write the spare plane)
+    int shell = meta[v0].shell;
     TC cc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) cc[t] = coef[(shell * NT + t) * 64 + lane];
-    TS* const out_row = fout + row + x;
-    auto collide = [&](int v, TC f) {
-        if (v >= next) {
-            ++shell;
-            next += P.K;
+    auto collide = [&](auto fast, int v, TC f) {
+        const VelMeta& M = meta[v];
+        if (M.shell != shell) {
+            shell = M.shell;
 #pragma unroll
             for (int t = 0; t < NT; ++t) cc[t] = coef[(shell * NT + t) * 64 + lane];
         }
@@ -191,16 +192,29 @@ __global__ __launch_bounds__(1024) void k_stream_collide(const TS* __restrict__ 
         TC feq = cc[0] * R.H[0];
 #pragma unroll
         for (int t = 1; t < NT; ++t) feq += cc[t] * R.H[t];
-        const TC om = a0 - ax * R.cth - ay * R.sth;
-        const TC fn = f + om * (feq - f);
-        if (active) out_row[(size_t)v * (size_t)P.S] = (TS)fn;
+        const TC om_ = a0 - ax * R.cth - ay * R.sth;
+        const TC fn = f + om_ * (feq - f);
+        TS* dst = reinterpret_cast<TS*>(outb + M.woff + ocb);
+        if (decltype(fast)::value || active) *dst = (TS)fn;
     };
+    auto phase4 = [&](auto fast) {
 #pragma unroll
-    for (int k = 0; k < VPT; ++k) {
-        const int v = v0 + k;
-        if (v < v1) collide(v, fs[k]);
-    }
-    for (int v = v0 + VPT; v < v1; ++v) collide(v, stream(v));
+        for (int kb = 0; kb < VPT / LB; ++kb) {
+            if (kb < nbatch) {
+#pragma unroll
+                for (int b = 0; b < LB; ++b) collide(fast, v0 + kb * LB + b, fs[kb * LB + b]);
+            }
+        }
+        for (int v = v0 + VPT; v < v0 + P.chunk; ++v) {
+            TC r[4];
+            load4(fast, v, r);
+            collide(fast, v, bilin(v, r));
+        }
+    };
+    if (interior)
+        phase4(std::true_type{});
+    else
+        phase4(std::false_type{});
 }
 
 // Initial populations: the truncated equilibrium of given fields, one thread
@@ -291,7 +305,7 @@ hipError_t launch_sc_t(int waves, const SCParams& p, hipStream_t st)
     if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_stream_collide<TS, TC, NM, VPT>), dim3((unsigned)tiles), dim3(64 * waves), lds, st,
                        static_cast<const TS*>(p.fin), static_cast<TS*>(p.fout), static_cast<const VelRec<TC>*>(p.vel),
-                       p.G, p.Pc, p);
+                       p.meta, p.G, p.Pc, p);
     return hipGetLastError();
 }
 

@@ -33,6 +33,25 @@ struct alignas(16) VelRec {
 };
 static_assert(sizeof(VelRec<float>) == 32 * 4, "VelRec layout");
 
+// Integer per-velocity data of the fused kernel, also read with scalar loads.
+//   roff   byte offset of the velocity's plane in the input buffer
+//   woff   byte offset of its plane in the output buffer
+//   dx     byte shift to the upwind column, -sgn(cos th) * element size
+//   sy     upwind row sign sgn(sin th) as +-1
+//   shell  radial shell index i (row of the equilibrium coefficients)
+// The table is padded past nvel with null entries (zero weights in VelRec,
+// roff = 0, woff = the spare plane at the end of each buffer, shell = Np-1),
+// so that every wave processes whole load batches without range checks.
+struct alignas(16) VelMeta {
+    long long roff, woff;
+    int dx, sy, shell, pad;
+};
+static_assert(sizeof(VelMeta) == 32, "VelMeta layout");
+
+// Velocities per load batch and the padding of the velocity tables.
+#define RLBM_LB 8
+#define RLBM_VPAD (RLBM_LB * 16)
+
 // Host-side quadrature and coefficient tables (FP64).
 struct HostQuad {
     int Np = 0, K = 0, N = 0, nvel = 0, rotate = 1;
@@ -147,7 +166,8 @@ __host__ __device__ inline void shell_coeffs(const double* __restrict__ Gs, cons
 struct SCParams {
     const void* fin;
     void* fout;
-    const void* vel;       // VelRec<TC>[nvel]
+    const void* vel;       // VelRec<TC>[nvel + RLBM_VPAD]
+    const VelMeta* meta;   // [nvel + RLBM_VPAD]
     const double* G;       // [Np][NMAX+1][NMAX+1]
     const double* Pc;
     int nx, ny, nvel, K, Np, N;
@@ -155,7 +175,7 @@ struct SCParams {
     long long S;
     double rate;           // dt / tau (0 for tau = inf)
     int* flag;
-    int chunk;             // velocities per wave
+    int chunk;             // velocities per wave, a multiple of RLBM_LB
 };
 
 // Launchers (kernels.hip).
