@@ -22,8 +22,8 @@ struct rlbm_ctx_s {
     double* d_fields = nullptr;
     double* d_partials = nullptr;
     int* d_flag = nullptr;
-    void* d_vel = nullptr;               // VelRec<TC>[nvel + RLBM_VPAD]
-    VelMeta* d_meta = nullptr;           // [nvel + RLBM_VPAD]
+    void* d_srec = nullptr;              // SRec<TC>[nvel + RLBM_VPAD]
+    void* d_crec = nullptr;              // CRec<TC, NM>[nvel + RLBM_VPAD]
     VelRec<double>* d_veld = nullptr;    // FP64 table for init and fields [nvel]
     double* d_G = nullptr;
     double* d_Pc = nullptr;
@@ -70,12 +70,63 @@ int nmax_of(int N) { return N <= 3 ? 3 : (N <= 5 ? 5 : 7); }
 
 void free_tables(rlbm_ctx c)
 {
-    if (c->d_vel) (void)hipFree(c->d_vel);
-    if (c->d_meta) (void)hipFree(c->d_meta);
+    if (c->d_srec) (void)hipFree(c->d_srec);
+    if (c->d_crec) (void)hipFree(c->d_crec);
     if (c->d_veld) (void)hipFree(c->d_veld);
     if (c->d_G) (void)hipFree(c->d_G);
     if (c->d_Pc) (void)hipFree(c->d_Pc);
-    c->d_vel = nullptr; c->d_meta = nullptr; c->d_veld = nullptr; c->d_G = nullptr; c->d_Pc = nullptr;
+    c->d_srec = nullptr; c->d_crec = nullptr; c->d_veld = nullptr; c->d_G = nullptr; c->d_Pc = nullptr;
+}
+
+template <typename T, int NM>
+int upload_tables_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, long long S, int precision)
+{
+    const size_t nv = c->q.nvel, npad = nv + RLBM_VPAD;
+    const long long es = (long long)elem_size(precision);
+    std::vector<SRec<T>> sr(npad);
+    std::vector<CRec<T, NM>> cr(npad);
+    for (size_t v = 0; v < npad; ++v) {
+        const bool real = v < nv;
+        SRec<T>& A = sr[v];
+        CRec<T, NM>& B = cr[v];
+        std::memset(&A, 0, sizeof(A));
+        std::memset(&B, 0, sizeof(B));
+        A.roff = real ? (long long)v * S * es : 0;
+        A.dx = real ? (vd[v].sx > 0 ? -1 : 1) * (int)es : -(int)es;
+        A.sy = real ? (vd[v].sy > 0 ? 1 : -1) : 1;
+        B.woff = (long long)(real ? v : nv) * S * es;
+        B.shell = real ? (int)(v / c->q.K) : c->q.Np - 1;
+        if (!real) continue;
+        const VelRec<double>& R = vd[v];
+        A.w[0] = (T)R.w00; A.w[1] = (T)R.w10; A.w[2] = (T)R.w01; A.w[3] = (T)R.w11;
+        for (int j = 0; j < (int)(sizeof(A.P) / sizeof(T)); ++j) A.P[j] = (T)R.P[j];
+        for (int t = 0; t < 2 * NM + 1; ++t) B.H[t] = (T)R.H[t];
+        B.cth = (T)R.cth; B.sth = (T)R.sth;
+    }
+    hipError_t e;
+    if ((e = hipMalloc(&c->d_srec, npad * sizeof(SRec<T>))) != hipSuccess) return fail(c, RLBM_ENOMEM, "table alloc");
+    if ((e = hipMalloc(&c->d_crec, npad * sizeof(CRec<T, NM>))) != hipSuccess) return fail(c, RLBM_ENOMEM, "table alloc");
+    if ((e = hipMemcpy(c->d_srec, sr.data(), npad * sizeof(SRec<T>), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(c, e, "table upload");
+    if ((e = hipMemcpy(c->d_crec, cr.data(), npad * sizeof(CRec<T, NM>), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(c, e, "table upload");
+    return RLBM_OK;
+}
+
+template <typename T>
+int upload_tables_p(rlbm_ctx c, const std::vector<VelRec<double>>& vd, long long S, int precision)
+{
+    switch (nmax_of(c->q.N)) {
+        case 3: return upload_tables_t<T, 3>(c, vd, S, precision);
+        case 5: return upload_tables_t<T, 5>(c, vd, S, precision);
+        default: return upload_tables_t<T, 7>(c, vd, S, precision);
+    }
+}
+
+int upload_kernel_tables(rlbm_ctx c, const std::vector<VelRec<double>>& vd, long long S, int precision)
+{
+    if (precision == RLBM_F64) return upload_tables_p<double>(c, vd, S, precision);
+    return upload_tables_p<float>(c, vd, S, precision);
 }
 
 bool finite_arr(const double* a, long long S)
@@ -194,42 +245,9 @@ int rlbm_init_fields(rlbm_ctx c, int nx, int ny, const double* n, const double* 
     if ((e = hipMemcpy(c->d_Pc, c->q.Pc.data(), c->q.Pc.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(c, e, "table upload");
     // kernel tables, padded with null entries (zero weights, spare plane)
-    const size_t npad = nv + RLBM_VPAD;
-    std::vector<VelRec<double>> vpad(npad, VelRec<double>{});
-    for (size_t v = 0; v < nv; ++v) vpad[v] = vd[v];
-    std::vector<VelMeta> meta(npad);
-    const long long es = (long long)elem_size(precision);
-    for (size_t v = 0; v < npad; ++v) {
-        VelMeta& M = meta[v];
-        const bool real = v < nv;
-        M.roff = real ? (long long)v * S * es : 0;
-        M.woff = (long long)(real ? v : nv) * S * es;
-        M.dx = real ? (vd[v].sx > 0 ? -1 : 1) * (int)es : -(int)es;
-        M.sy = real ? (vd[v].sy > 0 ? 1 : -1) : 1;
-        M.shell = real ? (int)(v / c->q.K) : c->q.Np - 1;
-        M.pad = 0;
-    }
-    if ((e = hipMalloc(&c->d_meta, npad * sizeof(VelMeta))) != hipSuccess) return fail(c, RLBM_ENOMEM, "table alloc");
-    if ((e = hipMemcpy(c->d_meta, meta.data(), npad * sizeof(VelMeta), hipMemcpyHostToDevice)) != hipSuccess)
-        return hip_fail(c, e, "table upload");
-    if (precision == RLBM_F64) {
-        void* p = nullptr;
-        if ((e = hipMalloc(&p, npad * sizeof(VelRec<double>))) != hipSuccess) return fail(c, RLBM_ENOMEM, "table alloc");
-        if ((e = hipMemcpy(p, vpad.data(), npad * sizeof(VelRec<double>), hipMemcpyHostToDevice)) != hipSuccess)
-            return hip_fail(c, e, "table upload");
-        c->d_vel = p;
-    } else {
-        std::vector<VelRec<float>> vf(npad);
-        for (size_t v = 0; v < npad; ++v) {
-            const double* src = reinterpret_cast<const double*>(&vpad[v]);
-            float* dst = reinterpret_cast<float*>(&vf[v]);
-            for (int k = 0; k < 32; ++k) dst[k] = (float)src[k];
-        }
-        void* p = nullptr;
-        if ((e = hipMalloc(&p, npad * sizeof(VelRec<float>))) != hipSuccess) return fail(c, RLBM_ENOMEM, "table alloc");
-        if ((e = hipMemcpy(p, vf.data(), npad * sizeof(VelRec<float>), hipMemcpyHostToDevice)) != hipSuccess)
-            return hip_fail(c, e, "table upload");
-        c->d_vel = p;
+    {
+        const int rc = upload_kernel_tables(c, vd, S, precision);
+        if (rc != RLBM_OK) return rc;
     }
 
     // upload the fields and build f = f_eq
@@ -280,8 +298,8 @@ int rlbm_step(rlbm_ctx c, int nsteps)
     if (nsteps < 0) return fail(c, RLBM_EINVAL, "nsteps < 0");
     const int waves = c->waves ? c->waves : default_waves(c->prec, nmax_of(c->q.N), c->q.nvel);
     SCParams p;
-    p.vel = c->d_vel;
-    p.meta = c->d_meta;
+    p.srec = c->d_srec;
+    p.crec = c->d_crec;
     p.G = c->d_G;
     p.Pc = c->d_Pc;
     p.nx = c->nx; p.ny = c->ny; p.nvel = c->q.nvel; p.K = c->q.K; p.Np = c->q.Np; p.N = c->q.N;

@@ -46,8 +46,8 @@ __device__ __forceinline__ int wrap_idx(int i, int n, int bc)
 
 template <typename TS, typename TC, int NM, int VPT>
 __global__ __launch_bounds__(1024) void k_stream_collide(const TS* __restrict__ fin, TS* __restrict__ fout,
-                                                         const VelRec<TC>* __restrict__ vel,
-                                                         const VelMeta* __restrict__ meta,
+                                                         const SRec<TC>* __restrict__ srec,
+                                                         const CRec<TC, NM>* __restrict__ crec,
                                                          const double* __restrict__ Gtab,
                                                          const double* __restrict__ Pc, SCParams P)
 {
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(1024) void k_stream_collide(const TS* __restrict__ 
 
     auto ld = [](const char* base, unsigned off) -> TC { return (TC)*reinterpret_cast<const TS*>(base + off); };
     auto load4 = [&](auto fast, int v, TC* r) {
-        const VelMeta& M = meta[v];
+        const SRec<TC>& M = srec[v];
         const char* p0 = inb + M.roff;
         const char* p1 = p0 + (M.sy > 0 ? dmb : dpb);
         if (decltype(fast)::value) {
@@ -99,8 +99,8 @@ __global__ __launch_bounds__(1024) void k_stream_collide(const TS* __restrict__ 
         }
     };
     auto bilin = [&](int v, const TC* r) -> TC {
-        const VelRec<TC>& R = vel[v];
-        return R.w00 * r[0] + R.w10 * r[1] + R.w01 * r[2] + R.w11 * r[3];
+        const SRec<TC>& R = srec[v];
+        return R.w[0] * r[0] + R.w[1] * r[1] + R.w[2] * r[2] + R.w[3] * r[3];
     };
 
     // 1. stream and accumulate moments, LB velocities' loads in flight at once
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(1024) void k_stream_collide(const TS* __restrict__ 
                     const int v = v0 + kb * LB + b;
                     const TC f = bilin(v, raw[b]);
                     fs[kb * LB + b] = f;
-                    const VelRec<TC>& R = vel[v];
+                    const SRec<TC>& R = srec[v];
 #pragma unroll
                     for (int j = 0; j < NMOM; ++j) m[j] += R.P[j] * f;
                 }
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(1024) void k_stream_collide(const TS* __restrict__ 
             TC r[4];
             load4(fast, v, r);
             const TC f = bilin(v, r);
-            const VelRec<TC>& R = vel[v];
+            const SRec<TC>& R = srec[v];
 #pragma unroll
             for (int j = 0; j < NMOM; ++j) m[j] += R.P[j] * f;
         }
@@ -177,24 +177,23 @@ __global__ __launch_bounds__(1024) void k_stream_collide(const TS* __restrict__ 
     __syncthreads();
 
     // 4. equilibrium, relaxation, store (null table entries write the spare plane)
-    int shell = meta[v0].shell;
+    int shell = crec[v0].shell;
     TC cc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) cc[t] = coef[(shell * NT + t) * 64 + lane];
     auto collide = [&](auto fast, int v, TC f) {
-        const VelMeta& M = meta[v];
-        if (M.shell != shell) {
-            shell = M.shell;
+        const CRec<TC, NM>& R = crec[v];
+        if (R.shell != shell) {
+            shell = R.shell;
 #pragma unroll
             for (int t = 0; t < NT; ++t) cc[t] = coef[(shell * NT + t) * 64 + lane];
         }
-        const VelRec<TC>& R = vel[v];
         TC feq = cc[0] * R.H[0];
 #pragma unroll
         for (int t = 1; t < NT; ++t) feq += cc[t] * R.H[t];
         const TC om_ = a0 - ax * R.cth - ay * R.sth;
         const TC fn = f + om_ * (feq - f);
-        TS* dst = reinterpret_cast<TS*>(outb + M.woff + ocb);
+        TS* dst = reinterpret_cast<TS*>(outb + R.woff + ocb);
         if (decltype(fast)::value || active) *dst = (TS)fn;
     };
     auto phase4 = [&](auto fast) {
@@ -304,8 +303,8 @@ hipError_t launch_sc_t(int waves, const SCParams& p, hipStream_t st)
     const long long tiles = (long long)((p.nx + 63) / 64) * p.ny;
     if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_stream_collide<TS, TC, NM, VPT>), dim3((unsigned)tiles), dim3(64 * waves), lds, st,
-                       static_cast<const TS*>(p.fin), static_cast<TS*>(p.fout), static_cast<const VelRec<TC>*>(p.vel),
-                       p.meta, p.G, p.Pc, p);
+                       static_cast<const TS*>(p.fin), static_cast<TS*>(p.fout),
+                       static_cast<const SRec<TC>*>(p.srec), static_cast<const CRec<TC, NM>*>(p.crec), p.G, p.Pc, p);
     return hipGetLastError();
 }
 
