@@ -30,6 +30,19 @@ METRIC = "GSVUPS + % HBM roofline; coarse-angle+MLP vs fine-angle speedup at equ
 BYTES_PER_SV = {"f32": 8, "f64": 16}
 
 
+def counter_traffic(precision, side):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this kernel and workload, or None if absent or taken on other sources."""
+    path = os.path.join(ROOT, "profiles", "stream_collide_%s_circular_%d.json" % (precision, side))
+    if not os.path.exists(path):
+        return None
+    from paper_2011_06856_amd.profile_summary import kernel_source_hash
+    d = json.load(open(path))
+    if d.get("kernel_sha256") != kernel_source_hash():
+        return None
+    return d.get("traffic_bytes")
+
+
 def gpu_run(cfg, steps, warmup, precision, waves):
     import torch
     from paper_2011_06856_amd import rlbm
@@ -116,7 +129,7 @@ def main():
                    "velocities": 256, "Kn": [0.01, 1.0], "runs": 2, "steps_per_run": a.steps,
                    "waves_per_group": runs[0.01]["waves"], "fields_finite": all(r["finite"] for r in runs.values())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(a.precision, a.side),
                      "kernel": "k_stream_collide", "algorithmic_bytes_per_sv": BYTES_PER_SV[a.precision],
                      "avg_launch_ms": launch_ms},
     }

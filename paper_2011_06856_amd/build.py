@@ -17,26 +17,28 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Wall", "-Wno-unused-result", "-Wno-unknown-warning-option"]
 
 
-def build(verbose=False):
+def build(verbose=False, out=SO, defines=()):
+    """Compile the library to `out`; `defines` are extra -D flags (variants)."""
     objs = []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
-        obj = os.path.join(CSRC, src.rsplit(".", 1)[0] + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "hip"]
-        cmd = [HIPCC] + FLAGS + lang + ["-c", path, "-o", obj]
+        tag = "%d_%x" % (os.getpid(), abs(hash((out, tuple(defines)))) & 0xffffff)
+        obj = os.path.join(CSRC, src.rsplit(".", 1)[0] + "." + tag + ".o")
+        lang = ["-x", "hip"]
+        cmd = [HIPCC] + FLAGS + ["-D" + d for d in defines] + lang + ["-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
         objs.append(obj)
-    tmp = SO + ".tmp%d" % os.getpid()
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, SO)
+    os.replace(tmp, out)
     for o in objs:
         os.remove(o)
-    return SO
+    return out
 
 
 if __name__ == "__main__":

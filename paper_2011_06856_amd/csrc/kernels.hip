@@ -194,7 +194,11 @@ __global__ __launch_bounds__(1024) void k_stream_collide(const TS* __restrict__ 
         const TC om_ = a0 - ax * R.cth - ay * R.sth;
         const TC fn = f + om_ * (feq - f);
         TS* dst = reinterpret_cast<TS*>(outb + R.woff + ocb);
+#ifdef RLBM_NT_STORE
+        if (decltype(fast)::value || active) __builtin_nontemporal_store((TS)fn, dst);
+#else
         if (decltype(fast)::value || active) *dst = (TS)fn;
+#endif
     };
     auto phase4 = [&](auto fast) {
 #pragma unroll
@@ -313,8 +317,7 @@ hipError_t launch_sc_t(int waves, const SCParams& p, hipStream_t st)
 // coefficient evaluation, whose size grows with the order.
 template <typename TC, int NM>
 struct Vpt {
-    static constexpr int value = sizeof(TC) == 8 ? (NM <= 3 ? 32 : (NM <= 5 ? 24 : 16))
-                                                 : (NM <= 3 ? 64 : (NM <= 5 ? 40 : 24));
+    static constexpr int value = sizeof(TC) == 8 ? (NM <= 3 ? 32 : 16) : (NM <= 3 ? 64 : (NM <= 5 ? 48 : 32));
 };
 
 template <typename TS, typename TC>

@@ -71,7 +71,9 @@ struct alignas(16) CRec {
 };
 
 // Velocities per load batch and the padding of the velocity tables.
+#ifndef RLBM_LB
 #define RLBM_LB 8
+#endif
 #define RLBM_VPAD (RLBM_LB * 16)
 
 // Host-side quadrature and coefficient tables (FP64).

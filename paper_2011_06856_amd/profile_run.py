@@ -1,0 +1,47 @@
+"""Workload driver for rocprofv3 runs of the fused stream-and-collide kernel.
+
+Runs `--steps` steps of the circular-shock workload (side^2 periodic grid,
+Np=4 x K=64, order 3, Kn=0.01) at the given precision, then a device-to-device
+copy of exactly `--copy-mib` MiB (read once, written once) whose FETCH_SIZE /
+WRITE_SIZE readings calibrate the counters to bytes.
+
+    rocprofv3 --kernel-trace --stats -d OUT -o run --output-format csv -- \
+        python3 -m paper_2011_06856_amd.profile_run --steps 20
+    rocprofv3 --pmc FETCH_SIZE ... (same command), then --pmc WRITE_SIZE
+"""
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--precision", default="f32")
+    ap.add_argument("--side", type=int, default=1024)
+    ap.add_argument("--Kn", type=float, default=0.01)
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    a = ap.parse_args()
+    import torch
+    import workloads as W
+    from paper_2011_06856_amd import rlbm
+    cfg = W.circular_shock(a.side, Kn=a.Kn, steps=a.steps)
+    s = rlbm.Solver(cfg["Np"], cfg["K"], cfg["N"])
+    s.init_fields(cfg["nx"], cfg["ny"], *cfg["fields"], tau=cfg["tau"], dt=cfg["dt"], precision=a.precision)
+    s.step(a.steps)
+    torch.cuda.synchronize()
+    n = a.copy_mib * 1024 * 1024 // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print("profile_run: %d steps of %s (%s), then one %d MiB device copy" % (a.steps, cfg["name"], a.precision,
+                                                                          a.copy_mib), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,115 @@
+"""Summarise rocprofv3 CSV output of profile_run into profiles/.
+
+Usage:
+    python -m paper_2011_06856_amd.profile_summary --stats DIR --fetch DIR --write DIR \
+        --name stream_collide_f32_circular_1024 --command "..." --copy-mib 1024 \
+        --launch-bytes 2147483648
+
+Writes profiles/<name>.md (kernel timing table, counter readings, the copy
+calibration factors and the derived HBM traffic per launch) and
+profiles/<name>.json, which bench.py reads to fill its `traffic` field while
+the kernel source is unchanged (sha256 of the kernel sources recorded here).
+"""
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "rlbm_internal.h")]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()
+
+
+def _rows(d, suffix):
+    files = glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)
+    rows = []
+    for f in files:
+        rows += list(csv.DictReader(open(f)))
+    return rows
+
+
+def counter_per_kernel(d, counter):
+    out = {}
+    for r in _rows(d, "counter_collection.csv"):
+        if r["Counter_Name"] != counter:
+            continue
+        out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--stats", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--name", required=True)
+    ap.add_argument("--command", required=True)
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--kernel", default="k_stream_collide")
+    ap.add_argument("--launch-bytes", type=float, required=True, help="algorithmic bytes per launch")
+    a = ap.parse_args()
+
+    stats = _rows(a.stats, "kernel_stats.csv")
+    fetch = counter_per_kernel(a.fetch, "FETCH_SIZE")
+    write = counter_per_kernel(a.write, "WRITE_SIZE")
+    copy_kib = a.copy_mib * 1024.0
+
+    def pick(d, key):
+        vals = [v for k, vs in d.items() if key in k for v in vs]
+        return vals
+
+    kf, kw = pick(fetch, a.kernel), pick(write, a.kernel)
+    cf, cw = max(pick(fetch, "copyBuffer") or [0]), max(pick(write, "copyBuffer") or [0])
+    f_fac = copy_kib / cf if cf else None
+    w_fac = copy_kib / cw if cw else None
+    kf_avg = sum(kf) / len(kf) if kf else None
+    kw_avg = sum(kw) / len(kw) if kw else None
+    traffic = None
+    if kf_avg and kw_avg and f_fac and w_fac:
+        traffic = (kf_avg * f_fac + kw_avg * w_fac) * 1024.0
+    kstat = [r for r in stats if a.kernel in r["Name"]]
+    avg_ns = float(kstat[0]["AverageNs"]) if kstat else None
+
+    lines = ["# %s" % a.name, "",
+             "Command (run from the repository root on the GPU box):", "", "```", a.command, "```", "",
+             "## Kernel trace (rocprofv3 --kernel-trace --stats)", "",
+             "| kernel | calls | avg us | min us | max us | % |", "|---|---|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r["Percentage"])):
+        nm = r["Name"].split("(")[0][-60:]
+        lines.append("| %s | %s | %.1f | %.1f | %.1f | %.1f |" % (nm, r["Calls"], float(r["AverageNs"]) / 1e3,
+                                                                float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
+                                                                float(r["Percentage"])))
+    lines += ["", "## HBM counters (rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE; KiB per dispatch)", "",
+              "| quantity | value |", "|---|---|",
+              "| calibration copy size | %d MiB read + %d MiB written |" % (a.copy_mib, a.copy_mib),
+              "| FETCH_SIZE of the copy | %s KiB -> factor %s |" % (cf, "%.4f" % f_fac if f_fac else "n/a"),
+              "| WRITE_SIZE of the copy | %s KiB -> factor %s |" % (cw, "%.4f" % w_fac if w_fac else "n/a"),
+              "| %s FETCH_SIZE (avg of %d) | %s KiB |" % (a.kernel, len(kf), "%.1f" % kf_avg if kf_avg else "n/a"),
+              "| %s WRITE_SIZE (avg of %d) | %s KiB |" % (a.kernel, len(kw), "%.1f" % kw_avg if kw_avg else "n/a"),
+              "| traffic per launch (scaled) | %s bytes |" % ("%.4g" % traffic if traffic else "n/a"),
+              "| algorithmic bytes per launch | %.4g |" % a.launch_bytes,
+              "| traffic / algorithmic | %s |" % ("%.3f" % (traffic / a.launch_bytes) if traffic else "n/a"),
+              "| avg launch duration | %s us |" % ("%.1f" % (avg_ns / 1e3) if avg_ns else "n/a"),
+              "| algorithmic GB/s at that duration | %s |" % ("%.0f" % (a.launch_bytes / avg_ns) if avg_ns else "n/a"),
+              "", "Kernel sources sha256: `%s`" % kernel_source_hash(), ""]
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    md = os.path.join(ROOT, "profiles", a.name + ".md")
+    open(md, "w").write("\n".join(lines))
+    js = dict(name=a.name, command=a.command, kernel=a.kernel, avg_launch_ns=avg_ns, traffic_bytes=traffic,
+              fetch_kib=kf_avg, write_kib=kw_avg, fetch_factor=f_fac, write_factor=w_fac,
+              launch_bytes=a.launch_bytes, kernel_sha256=kernel_source_hash())
+    json.dump(js, open(os.path.join(ROOT, "profiles", a.name + ".json"), "w"), indent=1)
+    print(md)
+
+
+if __name__ == "__main__":
+    main()

@@ -11,7 +11,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-SO_PATH = os.path.join(_HERE, "librlbm.so")
+# RLBM_LIBRARY may name another build of the same library (kernel variants)
+SO_PATH = os.environ.get("RLBM_LIBRARY") or os.path.join(_HERE, "librlbm.so")
 
 RLBM_OK, RLBM_EINVAL, RLBM_ENOMEM, RLBM_EDEVICE, RLBM_ENONPHYS, RLBM_ESTATE = 0, -1, -2, -3, -4, -5
 RLBM_F64, RLBM_F32, RLBM_BF16DEV = 0, 1, 2
