@@ -84,7 +84,7 @@ def main():
              "## Kernel trace (rocprofv3 --kernel-trace --stats)", "",
              "| kernel | calls | avg us | min us | max us | % |", "|---|---|---|---|---|---|"]
     for r in sorted(stats, key=lambda r: -float(r["Percentage"])):
-        nm = r["Name"].split("(")[0][-60:]
+        nm = r["Name"].replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0][:70]
         lines.append("| %s | %s | %.1f | %.1f | %.1f | %.1f |" % (nm, r["Calls"], float(r["AverageNs"]) / 1e3,
                                                                 float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
                                                                 float(r["Percentage"])))
