@@ -148,6 +148,68 @@ int rlbm_set_populations(rlbm_ctx ctx, const void* host, size_t bytes);
 int rlbm_set_waves(rlbm_ctx ctx, int waves);
 int rlbm_get_waves(rlbm_ctx ctx, int* waves);
 
+/* ------------------------------------------------------------------------ */
+/* Batched form: many independent problems of uneven grid size, quadrature   */
+/* and Knudsen number advance together.                                       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct rlbm_batch_s* rlbm_batch;
+
+/* One problem of a batch: the arguments of rlbm_init_quadrature and
+ * rlbm_init_fields (host field arrays [ny][nx], read during
+ * rlbm_batch_create only). */
+typedef struct {
+    int n_radial, n_angle, order, rotate;
+    int nx, ny;
+    const double *n, *T, *ux, *uy;
+    double tau, dt;
+    int bc_x, bc_y;
+} rlbm_problem;
+
+/*
+ * Create a batch of count problems at one population precision (RLBM_F32 or
+ * RLBM_F64), each initialised to local equilibrium as by rlbm_init_fields,
+ * with library-owned device memory; all work goes to hip_stream, which must
+ * not be the null stream (graphs cannot capture it); NULL makes the batch
+ * create and own a stream.  All problems must share the equilibrium order class (order <= 3,
+ * 4..5 or 6..7), since one kernel instance serves the launch.  RLBM_EINVAL as
+ * for the single-problem calls.
+ */
+int rlbm_batch_create(rlbm_batch* out, const rlbm_problem* probs, int count, int precision, void* hip_stream);
+int rlbm_batch_count(rlbm_batch b);
+
+/* The context of problem i (0-based), for rlbm_moments, rlbm_get_populations
+ * and rlbm_set_populations; owned by the batch, valid until
+ * rlbm_batch_destroy; must not be stepped on its own. */
+int rlbm_batch_problem(rlbm_batch b, int i, rlbm_ctx* ctx);
+
+/*
+ * Advance every problem nsteps steps.  Each step is one persistent launch
+ * whose work-groups take (problem, tile) items from per-XCD work queues until
+ * all are drained; pairs of steps are replayed from a captured HIP graph
+ * (the queue counters are cleared by a kernel node).  Asynchronous; allocates
+ * nothing after the first call for a shape.  rlbm_batch_step_eager issues the
+ * same launches without the graph.
+ */
+int rlbm_batch_step(rlbm_batch b, int nsteps);
+int rlbm_batch_step_eager(rlbm_batch b, int nsteps);
+int rlbm_batch_step_timed(rlbm_batch b, int nsteps, double* ms);
+
+/* Work-group shape (waves per group, 1..16; 0 = built-in choice). */
+int rlbm_batch_set_waves(rlbm_batch b, int waves);
+int rlbm_batch_get_waves(rlbm_batch b, int* waves);
+
+/*
+ * Autotuner: time `steps` graph-replayed steps for each candidate shape
+ * (waves per work-group), keep the fastest and report it; the populations are
+ * saved before and restored after, so the state is unchanged.  Allocates a
+ * temporary copy of the populations.
+ */
+int rlbm_batch_autotune(rlbm_batch b, const int* candidates, int ncand, int steps, int* best_waves, double* best_ms);
+
+const char* rlbm_batch_last_error(rlbm_batch b);
+int rlbm_batch_destroy(rlbm_batch b);
+
 /*
  * Host-side evaluations with the context's own tables; no device call is
  * made, so they run without a GPU.

@@ -5,31 +5,6 @@
 
 #include "rlbm_internal.h"
 
-struct rlbm_ctx_s {
-    HostQuad q;
-    std::string err;
-    int have_fields = 0;
-    int nx = 0, ny = 0, prec = RLBM_F64, bcx = 0, bcy = 0;
-    long long S = 0;
-    double tau = 0, dt = 1, rate = 0;
-    int waves = 0;
-    hipStream_t st = nullptr;
-    char* ws = nullptr;
-    bool ws_owned = false;
-    size_t ws_bytes = 0;
-    void* f[2] = {nullptr, nullptr};
-    int cur = 0;
-    double* d_fields = nullptr;
-    double* d_partials = nullptr;
-    int* d_flag = nullptr;
-    void* d_srec = nullptr;              // SRec<TC>[nvel + RLBM_VPAD]
-    void* d_crec = nullptr;              // CRec<TC, NM>[nvel + RLBM_VPAD]
-    VelRec<double>* d_veld = nullptr;    // FP64 table for init and fields [nvel]
-    double* d_G = nullptr;
-    double* d_Pc = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    long long steps = 0;
-};
 
 namespace {
 
@@ -65,8 +40,6 @@ Layout layout(int nvel, long long S, int prec)
     L.total = L.flag + 256;
     return L;
 }
-
-int nmax_of(int N) { return N <= 3 ? 3 : (N <= 5 ? 5 : 7); }
 
 void free_tables(rlbm_ctx c)
 {
@@ -137,6 +110,21 @@ bool finite_arr(const double* a, long long S)
 }
 
 }  // namespace
+
+SCParams make_params(rlbm_ctx c, int waves)
+{
+    SCParams p;
+    p.fin = p.fout = nullptr;
+    p.srec = c->d_srec;
+    p.crec = c->d_crec;
+    p.G = c->d_G;
+    p.Pc = c->d_Pc;
+    p.nx = c->nx; p.ny = c->ny; p.nvel = c->q.nvel; p.K = c->q.K; p.Np = c->q.Np; p.N = c->q.N;
+    p.bcx = c->bcx; p.bcy = c->bcy; p.S = c->S; p.rate = c->rate; p.flag = c->d_flag;
+    const int chunk = (c->q.nvel + waves - 1) / waves;
+    p.chunk = (chunk + RLBM_LB - 1) / RLBM_LB * RLBM_LB;
+    return p;
+}
 
 extern "C" {
 
@@ -297,15 +285,7 @@ int rlbm_step(rlbm_ctx c, int nsteps)
     if (!c->have_fields) return fail(c, RLBM_ESTATE, "rlbm_step before rlbm_init_fields");
     if (nsteps < 0) return fail(c, RLBM_EINVAL, "nsteps < 0");
     const int waves = c->waves ? c->waves : default_waves(c->prec, nmax_of(c->q.N), c->q.nvel);
-    SCParams p;
-    p.srec = c->d_srec;
-    p.crec = c->d_crec;
-    p.G = c->d_G;
-    p.Pc = c->d_Pc;
-    p.nx = c->nx; p.ny = c->ny; p.nvel = c->q.nvel; p.K = c->q.K; p.Np = c->q.Np; p.N = c->q.N;
-    p.bcx = c->bcx; p.bcy = c->bcy; p.S = c->S; p.rate = c->rate; p.flag = c->d_flag;
-    const int chunk = (c->q.nvel + waves - 1) / waves;
-    p.chunk = (chunk + RLBM_LB - 1) / RLBM_LB * RLBM_LB;
+    SCParams p = make_params(c, waves);
     for (int s = 0; s < nsteps; ++s) {
         p.fin = c->f[c->cur];
         p.fout = c->f[c->cur ^ 1];

@@ -44,19 +44,20 @@ __device__ __forceinline__ int wrap_idx(int i, int n, int bc)
     return i;
 }
 
+// One work-group tile of the fused step (64 sites of one row, all
+// velocities); `tile` indexes the tiles of the grid row-major, smem is the
+// work-group's dynamic LDS.
 template <typename TS, typename TC, int NM, int VPT>
-__global__ __launch_bounds__(1024) void k_stream_collide(const TS* __restrict__ fin, TS* __restrict__ fout,
-                                                         const SRec<TC>* __restrict__ srec,
-                                                         const CRec<TC, NM>* __restrict__ crec,
-                                                         const double* __restrict__ Gtab,
-                                                         const double* __restrict__ Pc, SCParams P)
+__device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restrict__ fout,
+                                        const SRec<TC>* __restrict__ srec, const CRec<TC, NM>* __restrict__ crec,
+                                        const double* __restrict__ Gtab, const double* __restrict__ Pc,
+                                        const SCParams& P, int tile, unsigned char* smem)
 {
     constexpr int NT = 2 * NM + 1;
     constexpr int NMOM = sizeof(TC) == 8 ? 9 : 8;   // FP32: T^yy = T^00 - T^xx
     constexpr int GS = (RLBM_NMAX + 1) * (RLBM_NMAX + 1);
     constexpr int LB = RLBM_LB;
     static_assert(VPT % LB == 0, "VPT must be a multiple of the load batch");
-    extern __shared__ __align__(16) unsigned char smem[];
     const int NW = blockDim.x >> 6;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -64,7 +65,6 @@ __global__ __launch_bounds__(1024) void k_stream_collide(const TS* __restrict__ 
     TC* coef = part + NW * NMOM * 64;                   // [Np][NT][64]
 
     const int ntx = (P.nx + 63) >> 6;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int ty = tile / ntx;
     const int tx = tile - ty * ntx;
     const int x = tx * 64 + lane;
@@ -220,6 +220,60 @@ __global__ __launch_bounds__(1024) void k_stream_collide(const TS* __restrict__ 
         phase4(std::false_type{});
 }
 
+template <typename TS, typename TC, int NM, int VPT>
+__global__ __launch_bounds__(1024) void k_stream_collide(const TS* __restrict__ fin, TS* __restrict__ fout,
+                                                         const SRec<TC>* __restrict__ srec,
+                                                         const CRec<TC, NM>* __restrict__ crec,
+                                                         const double* __restrict__ Gtab,
+                                                         const double* __restrict__ Pc, SCParams P)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    sc_tile<TS, TC, NM, VPT>(fin, fout, srec, crec, Gtab, Pc, P, xcd_remap(blockIdx.x, gridDim.x), smem);
+}
+
+// Batched form: many independent problems advance one step in one
+// persistent launch.  The (problem, tile) items are split into 8 contiguous
+// ranges, one per XCD; a work-group takes items from its own XCD's range
+// through an atomic counter (neighbouring rows stay in that XCD's L2) and,
+// once it is drained, from the other ranges in turn.  Every work-group leaves
+// when all ranges are drained.
+template <typename TS, typename TC, int NM, int VPT>
+__global__ __launch_bounds__(1024) void k_batch_step(const BatchDesc* __restrict__ descs, int nprob,
+                                                     int* __restrict__ counters, const int* __restrict__ bounds,
+                                                     int parity, const double* __restrict__ Pc)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int item_sh;
+    const int home = blockIdx.x & 7;
+    for (int q = 0; q < 8; ++q) {
+        const int part = (home + q) & 7;
+        const int end = bounds[part + 1];
+        for (;;) {
+            if (threadIdx.x == 0) item_sh = bounds[part] + atomicAdd(&counters[part * 16], 1);
+            __syncthreads();
+            const int item = __builtin_amdgcn_readfirstlane(item_sh);
+            __syncthreads();
+            if (item >= end) break;
+            int p = 0;   // problem owning the item: items of a problem are contiguous
+            int step = 1;
+            while (step * 2 <= nprob) step *= 2;
+            for (; step > 0; step >>= 1)
+                if (p + step < nprob && descs[p + step].item0 <= item) p += step;
+            const BatchDesc& D = descs[p];
+            sc_tile<TS, TC, NM, VPT>(static_cast<const TS*>(D.f[parity]), static_cast<TS*>(D.f[parity ^ 1]),
+                                     static_cast<const SRec<TC>*>(D.P.srec),
+                                     static_cast<const CRec<TC, NM>*>(D.P.crec), D.P.G, Pc, D.P,
+                                     item - D.item0, smem);
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void k_reset_counters(int* counters)
+{
+    if (threadIdx.x < 8) counters[threadIdx.x * 16] = 0;
+}
+
 // Initial populations: the truncated equilibrium of given fields, one thread
 // per site.  fields = [n | T | U^x | U^y], each S doubles.
 template <typename TS, int NM>
@@ -331,6 +385,43 @@ hipError_t launch_sc_n(int nmax, int waves, const SCParams& p, hipStream_t st)
     return hipErrorInvalidValue;
 }
 
+template <typename TS, typename TC, int NM, int VPT>
+size_t batch_lds(int waves, int max_np)
+{
+    constexpr int NT = 2 * NM + 1;
+    constexpr int NMOM = sizeof(TC) == 8 ? 9 : 8;
+    return (size_t)waves * NMOM * 64 * sizeof(TC) + (size_t)max_np * NT * 64 * sizeof(TC);
+}
+
+template <typename TS, typename TC, int NM, int VPT>
+hipError_t launch_batch_t(int waves, int grid, const BatchDesc* descs, int nprob, int* counters, const int* bounds,
+                          int parity, const double* Pc, int max_np, hipStream_t st)
+{
+    // the large-LDS attribute is set by batch_grid_t, before any graph capture
+    const size_t lds = batch_lds<TS, TC, NM, VPT>(waves, max_np);
+    if (lds > 160 * 1024 - 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_batch_step<TS, TC, NM, VPT>), dim3(grid), dim3(64 * waves), lds, st, descs, nprob,
+                       counters, bounds, parity, Pc);
+    return hipGetLastError();
+}
+
+// Resident work-groups for a persistent launch: occupancy per CU times CUs.
+template <typename TS, typename TC, int NM, int VPT>
+int batch_grid_t(int waves, int max_np)
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    const size_t lds = batch_lds<TS, TC, NM, VPT>(waves, max_np);
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_step<TS, TC, NM, VPT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_batch_step<TS, TC, NM, VPT>),
+                                                     64 * waves, lds) != hipSuccess)
+        return 0;
+    return per * cus;
+}
+
 template <typename TS>
 hipError_t launch_init_t(int nmax, const double* fields, void* f, const VelRec<double>* vel, const double* G,
                          const double* Pc, long long S, int K, int Np, hipStream_t st)
@@ -361,6 +452,49 @@ int default_waves(int prec, int nmax, int nvel)
 }
 
 int fields_blocks(long long S) { return (int)((S + 255) / 256); }
+
+hipError_t launch_batch_step(int prec, int nmax, int waves, int grid, const BatchDesc* descs, int nprob,
+                             int* counters, const int* bounds, int parity, const double* Pc, int max_np,
+                             hipStream_t st)
+{
+    if (waves < 1 || waves > 16 || grid < 1) return hipErrorInvalidValue;
+#define RLBM_BATCH_CASE(TS, TC, NM)                                                                            \
+    return launch_batch_t<TS, TC, NM, Vpt<TC, NM>::value>(waves, grid, descs, nprob, counters, bounds, parity, Pc, \
+                                                          max_np, st)
+    if (prec == RLBM_F32) {
+        if (nmax == 3) RLBM_BATCH_CASE(float, float, 3);
+        if (nmax == 5) RLBM_BATCH_CASE(float, float, 5);
+        if (nmax == 7) RLBM_BATCH_CASE(float, float, 7);
+    } else if (prec == RLBM_F64) {
+        if (nmax == 3) RLBM_BATCH_CASE(double, double, 3);
+        if (nmax == 5) RLBM_BATCH_CASE(double, double, 5);
+        if (nmax == 7) RLBM_BATCH_CASE(double, double, 7);
+    }
+#undef RLBM_BATCH_CASE
+    return hipErrorInvalidValue;
+}
+
+int batch_grid(int prec, int nmax, int waves, int max_np)
+{
+#define RLBM_GRID_CASE(TS, TC, NM) return batch_grid_t<TS, TC, NM, Vpt<TC, NM>::value>(waves, max_np)
+    if (prec == RLBM_F32) {
+        if (nmax == 3) RLBM_GRID_CASE(float, float, 3);
+        if (nmax == 5) RLBM_GRID_CASE(float, float, 5);
+        if (nmax == 7) RLBM_GRID_CASE(float, float, 7);
+    } else if (prec == RLBM_F64) {
+        if (nmax == 3) RLBM_GRID_CASE(double, double, 3);
+        if (nmax == 5) RLBM_GRID_CASE(double, double, 5);
+        if (nmax == 7) RLBM_GRID_CASE(double, double, 7);
+    }
+#undef RLBM_GRID_CASE
+    return 0;
+}
+
+hipError_t launch_reset_counters(int* counters, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, st, counters);
+    return hipGetLastError();
+}
 
 hipError_t launch_init(int prec, int nmax, const double* fields, void* f, const VelRec<double>* vel, const double* G,
                        const double* Pc, int nx, int ny, int nvel, int K, int Np, hipStream_t st)

@@ -202,6 +202,44 @@ struct SCParams {
     int chunk;             // velocities per wave, a multiple of RLBM_LB
 };
 
+// One problem of a batch: its buffers, tables and step parameters, and the
+// index of its first work item.
+struct BatchDesc {
+    void* f[2];
+    SCParams P;            // srec, crec, G and the scalars (fin/fout unused)
+    int item0, tiles;
+};
+
+// A simulation context (the opaque rlbm_ctx of the C ABI).
+struct rlbm_ctx_s {
+    HostQuad q;
+    std::string err;
+    int have_fields = 0;
+    int nx = 0, ny = 0, prec = RLBM_F64, bcx = 0, bcy = 0;
+    long long S = 0;
+    double tau = 0, dt = 1, rate = 0;
+    int waves = 0;
+    hipStream_t st = nullptr;
+    char* ws = nullptr;
+    bool ws_owned = false;
+    size_t ws_bytes = 0;
+    void* f[2] = {nullptr, nullptr};
+    int cur = 0;
+    double* d_fields = nullptr;
+    double* d_partials = nullptr;
+    int* d_flag = nullptr;
+    void* d_srec = nullptr;              // SRec<TC>[nvel + RLBM_VPAD]
+    void* d_crec = nullptr;              // CRec<TC, NM>[nvel + RLBM_VPAD]
+    VelRec<double>* d_veld = nullptr;    // FP64 table for init and fields [nvel]
+    double* d_G = nullptr;
+    double* d_Pc = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    long long steps = 0;
+};
+
+inline int nmax_of(int N) { return N <= 3 ? 3 : (N <= 5 ? 5 : 7); }
+SCParams make_params(rlbm_ctx c, int waves);   // capi.cpp
+
 // Launchers (kernels.hip).
 hipError_t launch_init(int prec, int nmax, const double* fields, void* f, const VelRec<double>* vel, const double* G,
                        const double* Pc, int nx, int ny, int nvel, int K, int Np, hipStream_t st);
@@ -209,6 +247,11 @@ hipError_t launch_stream_collide(int prec, int nmax, int waves, const SCParams& 
 hipError_t launch_fields(int prec, const void* f, const VelRec<double>* vel, double* out, double* partials,
                          int* flag, int nx, int ny, int nvel, hipStream_t st);
 hipError_t launch_landau_probe(const double* mom, double* out, int count, hipStream_t st);
+hipError_t launch_batch_step(int prec, int nmax, int waves, int grid, const BatchDesc* descs, int nprob,
+                             int* counters, const int* bounds, int parity, const double* Pc, int max_np,
+                             hipStream_t st);
+hipError_t launch_reset_counters(int* counters, hipStream_t st);
+int batch_grid(int prec, int nmax, int waves, int max_np);
 int default_waves(int prec, int nmax, int nvel);
 int max_vpt(int prec, int nmax);
 int fields_blocks(long long S);

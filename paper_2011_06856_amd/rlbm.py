@@ -43,6 +43,18 @@ SIGNATURES = [
     ("rlbm_host_feq", ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]),
     ("rlbm_host_landau", ctypes.c_int, [_dp, _dp]),
     ("rlbm_device_landau", ctypes.c_int, [ctypes.c_int, _dp, _dp]),
+    ("rlbm_batch_create", ctypes.c_int, [ctypes.POINTER(_vp), _vp, ctypes.c_int, ctypes.c_int, _vp]),
+    ("rlbm_batch_count", ctypes.c_int, [_vp]),
+    ("rlbm_batch_problem", ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(_vp)]),
+    ("rlbm_batch_step", ctypes.c_int, [_vp, ctypes.c_int]),
+    ("rlbm_batch_step_eager", ctypes.c_int, [_vp, ctypes.c_int]),
+    ("rlbm_batch_step_timed", ctypes.c_int, [_vp, ctypes.c_int, _dp]),
+    ("rlbm_batch_set_waves", ctypes.c_int, [_vp, ctypes.c_int]),
+    ("rlbm_batch_get_waves", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
+    ("rlbm_batch_autotune", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_int), _dp]),
+    ("rlbm_batch_last_error", ctypes.c_char_p, [_vp]),
+    ("rlbm_batch_destroy", ctypes.c_int, [_vp]),
     ("rlbm_last_error", ctypes.c_char_p, [_vp]),
     ("rlbm_destroy", ctypes.c_int, [_vp]),
 ]
@@ -110,10 +122,30 @@ def device_landau(moms):
     return out
 
 
+class RlbmProblem(ctypes.Structure):
+    """rlbm_problem of include/rlbm.h."""
+    _fields_ = [("n_radial", ctypes.c_int), ("n_angle", ctypes.c_int), ("order", ctypes.c_int),
+                ("rotate", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("n", _dp), ("T", _dp), ("ux", _dp), ("uy", _dp),
+                ("tau", ctypes.c_double), ("dt", ctypes.c_double), ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int)]
+
+
 class Solver:
     """One simulation context (rlbm_ctx)."""
 
+    @classmethod
+    def view(cls, handle, Np, K, N, nx, ny, precision):
+        """Non-owning view of a context owned by a batch."""
+        s = cls.__new__(cls)
+        s._h, s._owned = handle, False
+        s.Np, s.K, s.N = Np, K, N
+        s.nvel = lib().rlbm_nvel(handle)
+        s.nx, s.ny, s.precision = nx, ny, precision
+        s.workspace = None
+        return s
+
     def __init__(self, n_radial, n_angle, order=None, rotate=True):
+        self._owned = True
         order = n_radial - 1 if order is None else order
         h = _vp()
         rc = lib().rlbm_init_quadrature(ctypes.byref(h), int(n_radial), int(n_angle), int(order), 1 if rotate else 0)
@@ -128,9 +160,9 @@ class Solver:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and getattr(self, "_owned", True):
             lib().rlbm_destroy(h)
-            self._h = None
+        self._h = None
 
     def _check(self, rc):
         if rc == RLBM_OK:
@@ -218,3 +250,103 @@ class Solver:
         w = ctypes.c_int()
         self._check(lib().rlbm_get_waves(self._h, ctypes.byref(w)))
         return w.value
+
+
+class Batch:
+    """A batch of independent problems advanced together (rlbm_batch).
+
+    problems: list of dicts with keys Np, K, N, nx, ny, fields=(n, T, ux, uy),
+    tau, dt and optional bcx, bcy, rotate.
+    """
+
+    def __init__(self, problems, precision="f32", stream=None):
+        import torch
+        torch.cuda.init()
+        prec = PRECISIONS[precision]
+        arr = (RlbmProblem * len(problems))()
+        self._keep = []
+        for i, p in enumerate(problems):
+            shape = (p["ny"], p["nx"])
+            fl = [_arr(a, shape) if a is not None else None for a in p["fields"]]
+            self._keep.append(fl)
+            arr[i] = RlbmProblem(p["Np"], p["K"], p.get("N", p["Np"] - 1), 1 if p.get("rotate", True) else 0,
+                                 p["nx"], p["ny"], _p(fl[0]), _p(fl[1]), _p(fl[2]), _p(fl[3]),
+                                 float(p["tau"]), float(p["dt"]), int(p.get("bcx", 0)), int(p.get("bcy", 0)))
+        self.stream = stream   # None: the library creates and owns a stream
+        h = _vp()
+        rc = lib().rlbm_batch_create(ctypes.byref(h), ctypes.cast(arr, _vp), len(problems), prec,
+                                     _vp(stream.cuda_stream) if stream is not None else None)
+        if rc != RLBM_OK:
+            raise RlbmError(rc, "rlbm_batch_create failed")
+        self._h = h
+        self.problems = problems
+        self.precision = prec
+        self.views = []
+        for i, p in enumerate(problems):
+            c = _vp()
+            self._check(lib().rlbm_batch_problem(h, i, ctypes.byref(c)))
+            self.views.append(Solver.view(c, p["Np"], p["K"], p.get("N", p["Np"] - 1), p["nx"], p["ny"], prec))
+        self.nsv = sum(v.nvel * p["nx"] * p["ny"] for v, p in zip(self.views, problems))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self.views = []
+            lib().rlbm_batch_destroy(h)
+            self._h = None
+
+    def _check(self, rc):
+        if rc != RLBM_OK:
+            raise RlbmError(rc, lib().rlbm_batch_last_error(self._h).decode())
+
+    def __len__(self):
+        return len(self.views)
+
+    def problem(self, i):
+        return self.views[i]
+
+    def step(self, nsteps=1):
+        self._check(lib().rlbm_batch_step(self._h, int(nsteps)))
+
+    def step_eager(self, nsteps=1):
+        self._check(lib().rlbm_batch_step_eager(self._h, int(nsteps)))
+
+    def step_timed(self, nsteps):
+        ms = ctypes.c_double()
+        self._check(lib().rlbm_batch_step_timed(self._h, int(nsteps), ctypes.byref(ms)))
+        return ms.value
+
+    def set_waves(self, waves):
+        self._check(lib().rlbm_batch_set_waves(self._h, int(waves)))
+
+    def get_waves(self):
+        w = ctypes.c_int()
+        self._check(lib().rlbm_batch_get_waves(self._h, ctypes.byref(w)))
+        return w.value
+
+    def autotune(self, candidates=(2, 3, 4, 6, 8), steps=6, cache=None, key=None):
+        """Pick the fastest work-group shape; with `cache` (a JSON file path)
+        and `key`, reuse a stored choice or store the new one."""
+        import json
+        if cache and key and os.path.exists(cache):
+            try:
+                d = json.load(open(cache))
+                if key in d:
+                    self.set_waves(d[key]["waves"])
+                    return d[key]["waves"], d[key]["ms"]
+            except (ValueError, KeyError):
+                pass
+        c = (ctypes.c_int * len(candidates))(*candidates)
+        bw, bms = ctypes.c_int(), ctypes.c_double()
+        self._check(lib().rlbm_batch_autotune(self._h, c, len(candidates), int(steps), ctypes.byref(bw),
+                                              ctypes.byref(bms)))
+        if cache and key:
+            d = {}
+            if os.path.exists(cache):
+                try:
+                    d = json.load(open(cache))
+                except ValueError:
+                    d = {}
+            d[key] = {"waves": bw.value, "ms": bms.value}
+            json.dump(d, open(cache, "w"), indent=1)
+        return bw.value, bms.value
