@@ -83,6 +83,50 @@ def cpu_baseline(precision_unused, budget_s):
                 sample="%dx%d grid, Np=4 x K=64 (256 velocities), order 3, Kn=0.01, %d steps, FP64" % (side, side, nsteps))
 
 
+def batched_form(a):
+    """Batched form: 48 independent shock problems of uneven side (128..1024),
+    Knudsen number (1e-3..10, log-uniform) and angle count (48..128), Np=4,
+    FP32, advanced together by one persistent graph-replayed launch per step
+    with the autotuned work-group shape; compared with the same problems
+    stepped one after another by the plain per-problem launch."""
+    import torch
+    from paper_2011_06856_amd import rlbm
+    probs = W.batch_problems(48, seed=0, steps=a.steps)
+    print("bench: batched form, %d problems" % len(probs), file=sys.stderr, flush=True)
+    b = rlbm.Batch(probs, precision="f32")
+    waves, tune_ms = b.autotune(candidates=(2, 3, 4, 6, 8), steps=4,
+                                cache=os.path.join(ROOT, "_tune_cache.json") if a.tune_cache else None,
+                                key="batch48_seed0_gfx950_f32")
+    b.step(a.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = b.step_timed(a.steps)
+    wall = time.perf_counter() - t0
+    finite = all(np.isfinite(b.problem(i).moments(raise_nonphysical=False)[0]).all() for i in range(len(b)))
+    sv = float(b.nsv) * a.steps
+    del b
+    torch.cuda.empty_cache()
+    # plain path: each problem alone, same number of steps (timed on the library stream)
+    plain_ms = 0.0
+    for p in probs:
+        s = rlbm.Solver(p["Np"], p["K"], p["N"])
+        s.init_fields(p["nx"], p["ny"], *p["fields"], tau=p["tau"], dt=p["dt"], precision="f32")
+        s.step(a.warmup)
+        plain_ms += s.step_timed(a.steps)
+        del s
+    return {
+        "metric": METRIC, "value": sv / wall / 1e9, "unit": "GSVUPS", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": 1e3 * wall / a.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch48_uneven_shocks_np4", "problems": len(probs),
+                   "site_velocities_per_step": sv / a.steps, "autotuned_waves": waves,
+                   "fields_finite": bool(finite)},
+        "batched_vs_plain": {"batched_gsvups_events": sv / (ms * 1e-3) / 1e9,
+                             "plain_sequential_gsvups": sv / (plain_ms * 1e-3) / 1e9,
+                             "speedup": plain_ms / ms},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +137,8 @@ def main():
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--form", default="plain", choices=["plain", "batched"])
+    ap.add_argument("--tune-cache", action="store_true", help="reuse/store the autotuner choice in _tune_cache.json")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -100,6 +146,9 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if a.form == "batched":
+        print(json.dumps(batched_form(a)), flush=True)
+        return
     runs = {}
     for Kn in (0.01, 1.0):
         cfg = W.circular_shock(a.side, Kn=Kn, steps=a.steps)

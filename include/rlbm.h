@@ -207,6 +207,10 @@ int rlbm_batch_get_waves(rlbm_batch b, int* waves);
  */
 int rlbm_batch_autotune(rlbm_batch b, const int* candidates, int ncand, int steps, int* best_waves, double* best_ms);
 
+/* Launch shape for the current work-group shape: resident work-groups of the
+ * persistent launch and (problem, tile) work items per step. */
+int rlbm_batch_info(rlbm_batch b, int* grid, int* items);
+
 const char* rlbm_batch_last_error(rlbm_batch b);
 int rlbm_batch_destroy(rlbm_batch b);
 

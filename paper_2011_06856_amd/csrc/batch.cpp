@@ -322,6 +322,21 @@ int rlbm_batch_autotune(rlbm_batch b, const int* candidates, int ncand, int step
     return RLBM_OK;
 }
 
+int rlbm_batch_info(rlbm_batch b, int* grid, int* items)
+{
+    if (!b) return RLBM_EINVAL;
+    const int waves = effective_waves(b);
+    if (b->desc_waves != waves) {
+        drop_graph(b);
+        const int rc = upload_descs(b, waves);
+        if (rc != RLBM_OK) return rc;
+        b->desc_waves = waves;
+    }
+    if (grid) *grid = b->grid;
+    if (items) *items = b->total_items;
+    return RLBM_OK;
+}
+
 const char* rlbm_batch_last_error(rlbm_batch b) { return b ? b->err.c_str() : "null batch"; }
 
 int rlbm_batch_destroy(rlbm_batch b)

@@ -22,6 +22,14 @@
 
 #include "rlbm_internal.h"
 
+// Constant address space for read-only tables in device code (the host pass
+// of this file sees plain pointers).
+#ifdef __HIP_DEVICE_COMPILE__
+#define RLBM_CONST_AS __attribute__((address_space(4)))
+#else
+#define RLBM_CONST_AS
+#endif
+
 namespace {
 
 // Work-groups are dealt round-robin to the 8 XCDs (block b runs on XCD b % 8);
@@ -49,14 +57,23 @@ __device__ __forceinline__ int wrap_idx(int i, int n, int bc)
 // work-group's dynamic LDS.
 template <typename TS, typename TC, int NM, int VPT>
 __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restrict__ fout,
-                                        const SRec<TC>* __restrict__ srec, const CRec<TC, NM>* __restrict__ crec,
-                                        const double* __restrict__ Gtab, const double* __restrict__ Pc,
-                                        const SCParams& P, int tile, unsigned char* smem)
+                                        const SRec<TC>* srec_, const CRec<TC, NM>* crec_, const double* Gtab_,
+                                        const double* Pc_, const SCParams& P, int tile, unsigned char* smem)
 {
     constexpr int NT = 2 * NM + 1;
     constexpr int NMOM = sizeof(TC) == 8 ? 9 : 8;   // FP32: T^yy = T^00 - T^xx
     constexpr int GS = (RLBM_NMAX + 1) * (RLBM_NMAX + 1);
     constexpr int LB = RLBM_LB;
+    // The tables are read through the constant address space: they are not
+    // written during the kernel, so wave-uniform reads become scalar loads
+    // even where the pointers themselves come from memory (batched form).
+    using CSRec = const RLBM_CONST_AS SRec<TC>;
+    using CCRec = const RLBM_CONST_AS CRec<TC, NM>;
+    using CDbl = const RLBM_CONST_AS double;
+    CSRec* const srec = (CSRec*)srec_;
+    CCRec* const crec = (CCRec*)crec_;
+    CDbl* const Gtab = (CDbl*)Gtab_;
+    CDbl* const Pc = (CDbl*)Pc_;
     static_assert(VPT % LB == 0, "VPT must be a multiple of the load batch");
     const int NW = blockDim.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -86,9 +103,9 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
     const int v0 = w * P.chunk;
     const int nbatch = min(P.chunk, VPT) / LB;   // batches held in registers
 
-    auto ld = [](const char* base, unsigned off) -> TC { return (TC)*reinterpret_cast<const TS*>(base + off); };
-    auto load4 = [&](auto fast, int v, TC* r) {
-        const SRec<TC>& M = srec[v];
+    auto ld = [](const char* base, unsigned off) __attribute__((always_inline)) -> TC { return (TC)*reinterpret_cast<const TS*>(base + off); };
+    auto load4 = [&](auto fast, int v, TC* r) __attribute__((always_inline)) {
+        CSRec& M = srec[v];
         const char* p0 = inb + M.roff;
         const char* p1 = p0 + (M.sy > 0 ? dmb : dpb);
         if (decltype(fast)::value) {
@@ -98,8 +115,8 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
             r[0] = ld(p0, ocb); r[1] = ld(p0, osb); r[2] = ld(p1, ocb); r[3] = ld(p1, osb);
         }
     };
-    auto bilin = [&](int v, const TC* r) -> TC {
-        const SRec<TC>& R = srec[v];
+    auto bilin = [&](int v, const TC* r) __attribute__((always_inline)) -> TC {
+        CSRec& R = srec[v];
         return R.w[0] * r[0] + R.w[1] * r[1] + R.w[2] * r[2] + R.w[3] * r[3];
     };
 
@@ -108,7 +125,7 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
     TC m[NMOM];
 #pragma unroll
     for (int j = 0; j < NMOM; ++j) m[j] = TC(0);
-    auto phase1 = [&](auto fast) {
+    auto phase1 = [&](auto fast) __attribute__((always_inline)) {
 #pragma unroll
         for (int kb = 0; kb < VPT / LB; ++kb) {
             if (kb < nbatch) {
@@ -120,7 +137,7 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
                     const int v = v0 + kb * LB + b;
                     const TC f = bilin(v, raw[b]);
                     fs[kb * LB + b] = f;
-                    const SRec<TC>& R = srec[v];
+                    CSRec& R = srec[v];
 #pragma unroll
                     for (int j = 0; j < NMOM; ++j) m[j] += R.P[j] * f;
                 }
@@ -130,7 +147,7 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
             TC r[4];
             load4(fast, v, r);
             const TC f = bilin(v, r);
-            const SRec<TC>& R = srec[v];
+            CSRec& R = srec[v];
 #pragma unroll
             for (int j = 0; j < NMOM; ++j) m[j] += R.P[j] * f;
         }
@@ -164,7 +181,7 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
     for (int i = w; i < P.Np; i += NW) {
         TC* ci = coef + i * NT * 64 + lane;
         shell_coeffs<NM>(Gtab + (size_t)i * GS, Pc, fr.n, fr.T, fr.U0, fr.Ux, fr.Uy,
-                         [&](int mm, double cm, double sm) {
+                         [&](int mm, double cm, double sm) __attribute__((always_inline)) {
                              if (!fr.ok) cm = sm = 0.0;
                              if (mm == 0) {
                                  ci[0] = (TC)cm;
@@ -181,8 +198,8 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
     TC cc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) cc[t] = coef[(shell * NT + t) * 64 + lane];
-    auto collide = [&](auto fast, int v, TC f) {
-        const CRec<TC, NM>& R = crec[v];
+    auto collide = [&](auto fast, int v, TC f) __attribute__((always_inline)) {
+        CCRec& R = crec[v];
         if (R.shell != shell) {
             shell = R.shell;
 #pragma unroll
@@ -200,7 +217,7 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
         if (decltype(fast)::value || active) *dst = (TS)fn;
 #endif
     };
-    auto phase4 = [&](auto fast) {
+    auto phase4 = [&](auto fast) __attribute__((always_inline)) {
 #pragma unroll
         for (int kb = 0; kb < VPT / LB; ++kb) {
             if (kb < nbatch) {
@@ -258,12 +275,16 @@ __global__ __launch_bounds__(1024) void k_batch_step(const BatchDesc* __restrict
             int step = 1;
             while (step * 2 <= nprob) step *= 2;
             for (; step > 0; step >>= 1)
-                if (p + step < nprob && descs[p + step].item0 <= item) p += step;
-            const BatchDesc& D = descs[p];
+                if (p + step < nprob && ((const RLBM_CONST_AS BatchDesc*)descs)[p + step].item0 <= item)
+                    p += step;
+            // the descriptors are read through the constant address space
+            // (scalar loads): they are not written during the kernel
+            using CDesc = const RLBM_CONST_AS BatchDesc;
+            CDesc& D = ((CDesc*)descs)[p];
+            const SCParams P = D.P;
             sc_tile<TS, TC, NM, VPT>(static_cast<const TS*>(D.f[parity]), static_cast<TS*>(D.f[parity ^ 1]),
-                                     static_cast<const SRec<TC>*>(D.P.srec),
-                                     static_cast<const CRec<TC, NM>*>(D.P.crec), D.P.G, Pc, D.P,
-                                     item - D.item0, smem);
+                                     static_cast<const SRec<TC>*>(P.srec), static_cast<const CRec<TC, NM>*>(P.crec),
+                                     P.G, Pc, P, item - D.item0, smem);
             __syncthreads();
         }
     }
@@ -374,6 +395,12 @@ struct Vpt {
     static constexpr int value = sizeof(TC) == 8 ? (NM <= 3 ? 32 : 16) : (NM <= 3 ? 64 : (NM <= 5 ? 48 : 32));
 };
 
+// Values held per lane by the persistent batch kernel.
+template <typename TC, int NM>
+struct BVpt {
+    static constexpr int value = Vpt<TC, NM>::value;
+};
+
 template <typename TS, typename TC>
 hipError_t launch_sc_n(int nmax, int waves, const SCParams& p, hipStream_t st)
 {
@@ -459,8 +486,8 @@ hipError_t launch_batch_step(int prec, int nmax, int waves, int grid, const Batc
 {
     if (waves < 1 || waves > 16 || grid < 1) return hipErrorInvalidValue;
 #define RLBM_BATCH_CASE(TS, TC, NM)                                                                            \
-    return launch_batch_t<TS, TC, NM, Vpt<TC, NM>::value>(waves, grid, descs, nprob, counters, bounds, parity, Pc, \
-                                                          max_np, st)
+    return launch_batch_t<TS, TC, NM, BVpt<TC, NM>::value>(waves, grid, descs, nprob, counters, bounds, parity, Pc, \
+                                                           max_np, st)
     if (prec == RLBM_F32) {
         if (nmax == 3) RLBM_BATCH_CASE(float, float, 3);
         if (nmax == 5) RLBM_BATCH_CASE(float, float, 5);
@@ -476,7 +503,7 @@ hipError_t launch_batch_step(int prec, int nmax, int waves, int grid, const Batc
 
 int batch_grid(int prec, int nmax, int waves, int max_np)
 {
-#define RLBM_GRID_CASE(TS, TC, NM) return batch_grid_t<TS, TC, NM, Vpt<TC, NM>::value>(waves, max_np)
+#define RLBM_GRID_CASE(TS, TC, NM) return batch_grid_t<TS, TC, NM, BVpt<TC, NM>::value>(waves, max_np)
     if (prec == RLBM_F32) {
         if (nmax == 3) RLBM_GRID_CASE(float, float, 3);
         if (nmax == 5) RLBM_GRID_CASE(float, float, 5);

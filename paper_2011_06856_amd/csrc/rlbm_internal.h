@@ -157,9 +157,9 @@ __host__ __device__ inline Frame landau_frame(const double* m)
 // handed to emit(m, C_m, S_m) one harmonic at a time (few live registers).
 // Gs = G[shell] ([NMAX+1][NMAX+1]), zero beyond the expansion order, so that
 // harmonics above the order come out as zero.
-template <int NM, typename Emit>
-__host__ __device__ inline void shell_coeffs(const double* __restrict__ Gs, const double* __restrict__ Pc, double n,
-                                             double T, double U0, double Ux, double Uy, Emit emit)
+template <int NM, typename PT, typename Emit>
+__host__ __device__ inline void shell_coeffs(PT Gs, PT Pc, double n, double T, double U0, double Ux, double Uy,
+                                             Emit emit)
 {
     const double u2 = U0 * U0;
     double zr = 1.0, zi = 0.0;   // (U^x + i U^y)^m
@@ -170,7 +170,7 @@ __host__ __device__ inline void shell_coeffs(const double* __restrict__ Gs, cons
 #pragma unroll
         for (int r = 0; r + m <= NM; ++r) {
             // P_{m+r,m}(U^0) by Horner in (U^0)^2
-            const double* pc = Pc + (m * (RLBM_NMAX + 1) + r) * RLBM_PC_L;
+            PT pc = Pc + (m * (RLBM_NMAX + 1) + r) * RLBM_PC_L;
             double pk = pc[0];
 #pragma unroll
             for (int l = 1; 2 * l <= r; ++l) pk = pk * u2 + pc[l];
@@ -209,6 +209,7 @@ struct BatchDesc {
     SCParams P;            // srec, crec, G and the scalars (fin/fout unused)
     int item0, tiles;
 };
+static_assert(sizeof(BatchDesc) % 4 == 0, "BatchDesc is copied in 32-bit words");
 
 // A simulation context (the opaque rlbm_ctx of the C ABI).
 struct rlbm_ctx_s {

@@ -53,6 +53,7 @@ SIGNATURES = [
     ("rlbm_batch_get_waves", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
     ("rlbm_batch_autotune", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int,
                                            ctypes.POINTER(ctypes.c_int), _dp]),
+    ("rlbm_batch_info", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     ("rlbm_batch_last_error", ctypes.c_char_p, [_vp]),
     ("rlbm_batch_destroy", ctypes.c_int, [_vp]),
     ("rlbm_last_error", ctypes.c_char_p, [_vp]),
@@ -318,6 +319,12 @@ class Batch:
 
     def set_waves(self, waves):
         self._check(lib().rlbm_batch_set_waves(self._h, int(waves)))
+
+    def info(self):
+        """(resident work-groups of the persistent launch, work items per step)"""
+        g, it = ctypes.c_int(), ctypes.c_int()
+        self._check(lib().rlbm_batch_info(self._h, ctypes.byref(g), ctypes.byref(it)))
+        return g.value, it.value
 
     def get_waves(self):
         w = ctypes.c_int()
