@@ -127,6 +127,26 @@ def batched_form(a):
     }
 
 
+def learned_form(a):
+    """Learned form: 512^2 periodic shocks, Np=4; coarse K=24 plus the MLP
+    stress correction against the plain solver swept over K in 24..384, all
+    judged against plain K=384.  Reports the equal-error angle count K* per
+    field and the speedup wall(plain K*) / wall(coarse + MLP)."""
+    from paper_2011_06856_amd import learned as Lr
+    say = lambda m: print("bench: " + m, file=sys.stderr, flush=True)
+    r = Lr.study(side=a.side, steps=a.steps, train_seeds=range(a.train_seeds),
+                 eval_seeds=range(10000, 10000 + a.eval_seeds), epochs=a.epochs, log=say)
+    sp = [v for v in r["speedup"].values() if v]
+    return {
+        "metric": METRIC, "value": min(sp) if len(sp) == 3 else None, "unit": "x (wall plain K* / wall coarse+MLP)",
+        "n_gpus": 1, "steps": a.steps, "warmup": 0, "ms_per_step": 1e3 * r["wall_corrected_s"] / a.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "learned_shocks_%d_np4_k24_vs_k384" % a.side, "train_seeds": a.train_seeds,
+                   "eval_seeds": a.eval_seeds, "steps_per_run": a.steps, "epochs": a.epochs},
+        "learned": r,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,7 +157,10 @@ def main():
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--form", default="plain", choices=["plain", "batched"])
+    ap.add_argument("--form", default="plain", choices=["plain", "batched", "learned"])
+    ap.add_argument("--train-seeds", type=int, default=200, help="learned form: training seeds")
+    ap.add_argument("--eval-seeds", type=int, default=20, help="learned form: held-out seeds")
+    ap.add_argument("--epochs", type=int, default=10, help="learned form: training epochs")
     ap.add_argument("--tune-cache", action="store_true", help="reuse/store the autotuner choice in _tune_cache.json")
     a = ap.parse_args()
     if a.gpus != 1:
@@ -148,6 +171,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if a.form == "batched":
         print(json.dumps(batched_form(a)), flush=True)
+        return
+    if a.form == "learned":
+        print(json.dumps(learned_form(a)), flush=True)
         return
     runs = {}
     for Kn in (0.01, 1.0):

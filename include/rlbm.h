@@ -214,6 +214,75 @@ int rlbm_batch_info(rlbm_batch b, int* grid, int* items);
 const char* rlbm_batch_last_error(rlbm_batch b);
 int rlbm_batch_destroy(rlbm_batch b);
 
+/* ------------------------------------------------------------------------ */
+/* Learned form: an MLP correction of the traceless stress of a coarse-angle  */
+/* run, trained on fine-angle runs.                                           */
+/* ------------------------------------------------------------------------ */
+
+typedef struct rlbm_mlp_s* rlbm_mlp;
+
+/*
+ * A fully connected network in_dim -> hidden (n_hidden layers, GELU) ->
+ * out_dim, for batches of up to max_batch rows, its work on hip_stream.
+ * Parameters: one flat FP32 vector [W1 (hidden x in_dim, row-major), b1, W2,
+ * b2, ..., Wout (out_dim x hidden), bout], zero at creation.  The forward
+ * pass uses the weights rounded to bfloat16 (round to nearest even) with FP32
+ * accumulation; gradients are taken with respect to those rounded weights and
+ * applied by Adam to the FP32 master copy.
+ */
+int rlbm_mlp_create(rlbm_mlp* out, int in_dim, int hidden, int n_hidden, int out_dim, int max_batch,
+                    void* hip_stream);
+long rlbm_mlp_nparams(rlbm_mlp m);
+int rlbm_mlp_set_params(rlbm_mlp m, const float* host);   /* also resets Adam */
+int rlbm_mlp_get_params(rlbm_mlp m, float* host);
+int rlbm_mlp_get_grad(rlbm_mlp m, float* host);          /* last rlbm_mlp_grad result */
+
+/* Feature and output scales of the correction: network input k of a site is
+ * (field - in_mu[k]) / in_sig[k] for the 7 fields (n, eps, U^x, U^y, pi^xx,
+ * pi^xy, pi^yy); the stress change is out_mu + out_sig * output. */
+int rlbm_mlp_set_norm(rlbm_mlp m, const float* in_mu, const float* in_sig, const float* out_mu, const float* out_sig);
+
+/* Device pointers: dX [B][in_dim], dY [B][out_dim], dT [B][out_dim]. */
+int rlbm_mlp_forward(rlbm_mlp m, const float* dX, int B, float* dY);
+/* Loss 0.5/B sum (y - t)^2 and its gradient (kept inside; rlbm_mlp_get_grad). */
+int rlbm_mlp_grad(rlbm_mlp m, const float* dX, const float* dT, int B, double* loss);
+int rlbm_mlp_adam_step(rlbm_mlp m, float lr, float beta1, float beta2, float eps);
+
+/* Per-site fields of a context's current populations (FP64 moments and
+ * Landau frame), device [S][8] = n, eps, U^x, U^y, pi^xx, pi^xy, pi^yy, 0, where
+ * pi^ij = T^ij - (eps + P) U^i U^j - P delta^ij, P = eps/2 (Eq. ll-decomp). */
+int rlbm_site_stats(rlbm_ctx c, float* dstats);
+/* Network inputs of every site: the 7 fields of its 3x3 neighbourhood
+ * (periodic), normalised, device [S][64] (column 63 zero). */
+int rlbm_mlp_features(rlbm_ctx c, rlbm_mlp m, float* dX);
+/*
+ * In-loop correction: inputs, forward pass, and the predicted change
+ * (dT^xx, dT^xy, dT^yy), times scale, put into the populations through the
+ * m = 2 basis function p^2 {cos, sin}(2 theta):
+ *   f_v += w_v p_v^2 [(dT^xx - dT^yy) cos 2th_v + 2 dT^xy sin 2th_v] / (24 pi),
+ * which changes T^xx - T^yy and T^xy and leaves N^mu, T^00 and T^0i unchanged.
+ * relax = 0: the output is the change itself (dT = scale * output).
+ * relax = 1: the output is a target shear stress and the site relaxes
+ *            toward it, dT = scale * (output - pi) with pi the site's
+ *            current Landau-frame shear stress.
+ * Requires S <= max_batch and a shared stream.
+ */
+int rlbm_mlp_correct(rlbm_ctx c, rlbm_mlp m, float scale, int relax);
+/* The same change of the traceless stress from a device array [S][3] =
+ * (dT^xx, dT^xy, dT^yy), times scale (e.g. to give a local-equilibrium state
+ * a prescribed shear stress). */
+int rlbm_add_stress(rlbm_ctx c, const float* dstress, float scale);
+/* Resample src's populations onto dst's angle set: both contexts on the same
+ * grid and radial shells (same n_radial and rotation), any K each, FP32 or
+ * FP64.  Per shell the angular harmonics |m| <= M = (min(K_src, K_dst)-1)/2
+ * of src are evaluated at dst's angles, so every moment of angular order <= M
+ * (N^mu, T^munu) is kept.  Used to restrict a fine-angle state to a coarse
+ * one (training data of the learned correction) and to lift it back.
+ * Synchronous.  RLBM_EINVAL on mismatched grids or shells. */
+int rlbm_resample(rlbm_ctx src, rlbm_ctx dst);
+const char* rlbm_mlp_last_error(rlbm_mlp m);
+int rlbm_mlp_destroy(rlbm_mlp m);
+
 /*
  * Host-side evaluations with the context's own tables; no device call is
  * made, so they run without a GPU.

@@ -137,6 +137,19 @@ def landau(mom):
     return out, bad == 0
 
 
+def site_stats(mom):
+    """(n, eps, U^x, U^y, pi^xx, pi^xy, pi^yy) of one site from its nine
+    moments: Landau frame, then the shear stress of the Landau-Lifshitz
+    decomposition T^ij = (eps + P) U^i U^j + P delta^ij + pi^ij with the
+    massless equation of state P = eps / 2 (Sec. 2)."""
+    fr, ok = landau(mom)
+    if not ok:
+        return None
+    n, eps, ux, uy = fr[0], fr[1], fr[2], fr[3]
+    P, w = 0.5 * eps, 1.5 * eps
+    return np.array([n, eps, ux, uy, mom[6] - w * ux * ux - P, mom[7] - w * ux * uy, mom[8] - w * uy * uy - P])
+
+
 class Sim:
     """Lattice evolution on an nx x ny grid (Eq. discrete-rbe).
 

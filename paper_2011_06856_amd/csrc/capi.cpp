@@ -48,7 +48,8 @@ void free_tables(rlbm_ctx c)
     if (c->d_veld) (void)hipFree(c->d_veld);
     if (c->d_G) (void)hipFree(c->d_G);
     if (c->d_Pc) (void)hipFree(c->d_Pc);
-    c->d_srec = nullptr; c->d_crec = nullptr; c->d_veld = nullptr; c->d_G = nullptr; c->d_Pc = nullptr;
+    if (c->d_corr) (void)hipFree(c->d_corr);
+    c->d_srec = nullptr; c->d_crec = nullptr; c->d_veld = nullptr; c->d_corr = nullptr; c->d_G = nullptr; c->d_Pc = nullptr;
 }
 
 template <typename T, int NM>

@@ -236,6 +236,7 @@ struct rlbm_ctx_s {
     double* d_Pc = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     long long steps = 0;
+    double* d_corr = nullptr;            // learned correction: w p^2 {cos, sin} 2th per velocity
 };
 
 inline int nmax_of(int N) { return N <= 3 ? 3 : (N <= 5 ? 5 : 7); }

@@ -53,6 +53,23 @@ SIGNATURES = [
     ("rlbm_batch_get_waves", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
     ("rlbm_batch_autotune", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int,
                                            ctypes.POINTER(ctypes.c_int), _dp]),
+    ("rlbm_mlp_create", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, _vp]),
+    ("rlbm_mlp_nparams", ctypes.c_long, [_vp]),
+    ("rlbm_mlp_set_params", ctypes.c_int, [_vp, _vp]),
+    ("rlbm_mlp_get_params", ctypes.c_int, [_vp, _vp]),
+    ("rlbm_mlp_get_grad", ctypes.c_int, [_vp, _vp]),
+    ("rlbm_mlp_set_norm", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    ("rlbm_mlp_forward", ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp]),
+    ("rlbm_mlp_grad", ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _dp]),
+    ("rlbm_mlp_adam_step", ctypes.c_int, [_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
+    ("rlbm_site_stats", ctypes.c_int, [_vp, _vp]),
+    ("rlbm_mlp_features", ctypes.c_int, [_vp, _vp, _vp]),
+    ("rlbm_mlp_correct", ctypes.c_int, [_vp, _vp, ctypes.c_float, ctypes.c_int]),
+    ("rlbm_add_stress", ctypes.c_int, [_vp, _vp, ctypes.c_float]),
+    ("rlbm_resample", ctypes.c_int, [_vp, _vp]),
+    ("rlbm_mlp_last_error", ctypes.c_char_p, [_vp]),
+    ("rlbm_mlp_destroy", ctypes.c_int, [_vp]),
     ("rlbm_batch_info", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     ("rlbm_batch_last_error", ctypes.c_char_p, [_vp]),
     ("rlbm_batch_destroy", ctypes.c_int, [_vp]),
@@ -161,8 +178,8 @@ class Solver:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h and getattr(self, "_owned", True):
-            lib().rlbm_destroy(h)
+        if h and getattr(self, "_owned", True) and _L is not None:
+            _L.rlbm_destroy(h)
         self._h = None
 
     def _check(self, rc):
@@ -357,3 +374,120 @@ class Batch:
             d[key] = {"waves": bw.value, "ms": bms.value}
             json.dump(d, open(cache, "w"), indent=1)
         return bw.value, bms.value
+
+
+def _fptr(t):
+    """Device pointer of a contiguous float32 torch tensor."""
+    import torch
+    assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+    return _vp(t.data_ptr())
+
+
+def site_stats(solver):
+    """(S, 8) device tensor: n, eps, U^x, U^y, pi^xx, pi^xy, pi^yy, 0 per site."""
+    import torch
+    out = torch.empty((solver.nx * solver.ny, 8), dtype=torch.float32, device="cuda")
+    rc = lib().rlbm_site_stats(solver._h, _fptr(out))
+    if rc != RLBM_OK:
+        raise RlbmError(rc, "rlbm_site_stats failed")
+    return out
+
+
+def add_stress(solver, dstress, scale=1.0):
+    """Add a change of the traceless stress (device (S, 3) tensor: dT^xx,
+    dT^xy, dT^yy) to the populations, leaving N^mu and T^0mu unchanged."""
+    rc = lib().rlbm_add_stress(solver._h, _fptr(dstress), float(scale))
+    if rc != RLBM_OK:
+        raise RlbmError(rc, "rlbm_add_stress failed")
+
+
+def resample(src, dst):
+    """Resample src's populations onto dst's angle set (same grid and shells)."""
+    rc = lib().rlbm_resample(src._h, dst._h)
+    if rc != RLBM_OK:
+        raise RlbmError(rc, "rlbm_resample failed")
+
+
+class MLP:
+    """The learned correction network (rlbm_mlp): in_dim -> hidden^n_hidden -> out_dim."""
+
+    def __init__(self, in_dim=64, hidden=128, n_hidden=3, out_dim=3, max_batch=65536, stream=None):
+        h = _vp()
+        rc = lib().rlbm_mlp_create(ctypes.byref(h), in_dim, hidden, n_hidden, out_dim, max_batch,
+                                   _vp(stream.cuda_stream) if stream is not None else None)
+        if rc != RLBM_OK:
+            raise RlbmError(rc, "rlbm_mlp_create failed")
+        self._h = h
+        self.in_dim, self.hidden, self.n_hidden, self.out_dim, self.max_batch = in_dim, hidden, n_hidden, out_dim, max_batch
+        self.nparams = int(lib().rlbm_mlp_nparams(h))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _L is not None:
+            _L.rlbm_mlp_destroy(h)
+        self._h = None
+
+    def _check(self, rc):
+        if rc != RLBM_OK:
+            raise RlbmError(rc, lib().rlbm_mlp_last_error(self._h).decode())
+
+    def layer_shapes(self):
+        dims = [self.in_dim] + [self.hidden] * self.n_hidden + [self.out_dim]
+        return [(dims[i + 1], dims[i]) for i in range(len(dims) - 1)]
+
+    def init_params(self, seed=0):
+        """He-style uniform initialisation from the counter-based generator."""
+        import workloads as W
+        out, k = [], 0
+        for (o, i) in self.layer_shapes():
+            u = W.uniform(seed, k + np.arange(o * i))
+            k += o * i
+            lim = np.sqrt(6.0 / i) if o != self.out_dim else np.sqrt(1.0 / i)
+            out.append(((2 * u - 1) * lim).astype(np.float32))
+            out.append(np.zeros(o, dtype=np.float32))
+        p = np.concatenate(out)
+        self.set_params(p)
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.nparams
+        self._check(lib().rlbm_mlp_set_params(self._h, _vp(p.ctypes.data)))
+
+    def get_params(self):
+        p = np.empty(self.nparams, dtype=np.float32)
+        self._check(lib().rlbm_mlp_get_params(self._h, _vp(p.ctypes.data)))
+        return p
+
+    def get_grad(self):
+        g = np.empty(self.nparams, dtype=np.float32)
+        self._check(lib().rlbm_mlp_get_grad(self._h, _vp(g.ctypes.data)))
+        return g
+
+    def set_norm(self, in_mu, in_sig, out_mu, out_sig):
+        a = [np.ascontiguousarray(x, dtype=np.float32) for x in (in_mu, in_sig, out_mu, out_sig)]
+        self._keep_norm = a
+        self._check(lib().rlbm_mlp_set_norm(self._h, *[_vp(x.ctypes.data) for x in a]))
+
+    def forward(self, X):
+        import torch
+        Y = torch.empty((X.shape[0], self.out_dim), dtype=torch.float32, device="cuda")
+        self._check(lib().rlbm_mlp_forward(self._h, _fptr(X), int(X.shape[0]), _fptr(Y)))
+        return Y
+
+    def grad(self, X, T):
+        loss = ctypes.c_double()
+        self._check(lib().rlbm_mlp_grad(self._h, _fptr(X), _fptr(T), int(X.shape[0]), ctypes.byref(loss)))
+        return loss.value
+
+    def adam_step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self._check(lib().rlbm_mlp_adam_step(self._h, lr, b1, b2, eps))
+
+    def features(self, solver):
+        import torch
+        X = torch.empty((solver.nx * solver.ny, self.in_dim), dtype=torch.float32, device="cuda")
+        self._check(lib().rlbm_mlp_features(solver._h, self._h, _fptr(X)))
+        return X
+
+    def correct(self, solver, scale=1.0, relax=False):
+        self._check(lib().rlbm_mlp_correct(solver._h, self._h, float(scale), int(bool(relax))))

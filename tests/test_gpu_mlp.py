@@ -1,0 +1,265 @@
+"""GPU tests of the learned form's kernels: network forward, backward and
+Adam against the FP64 reference in oracle/mlp_oracle.py; site statistics,
+network inputs, the stress injection and angular resampling against the
+oracle's moments and Landau solve; and the correction channel's effect on a
+coarse-angle run."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import mlp_oracle as M
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _rl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2011_06856_amd import rlbm
+    rlbm.lib()
+    return rlbm
+
+
+def say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _cuda(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
+
+
+def _net_with_biases(rl, B, seed):
+    net = rl.MLP(max_batch=B)
+    p = net.init_params(seed=seed).astype(np.float64)
+    k = 0
+    for (o, i) in net.layer_shapes():
+        k += o * i
+        p[k:k + o] = (W.uniform(seed + 100, k + np.arange(o)) - 0.5) * 0.2
+        k += o
+    p = p.astype(np.float32)
+    net.set_params(p)
+    return net, p
+
+
+def _inputs(seed, B, d=64):
+    X = (W.uniform(seed, np.arange(B * d)).reshape(B, d) * 2 - 1) * 1.5
+    X[:, 63] = 0.0
+    return X
+
+
+def test_forward_matches_oracle():
+    rl = _rl()
+    B = 300                                   # 4 full row tiles of 64 and a ragged one
+    net, p = _net_with_biases(rl, B, 11)
+    X = _inputs(12, B)
+    say("mlp forward B=%d params=%d" % (B, net.nparams))
+    Y = net.forward(_cuda(X)).cpu().numpy().astype(np.float64)
+    Yo, _ = M.forward(p.astype(np.float64), net.layer_shapes(), X)
+    assert np.abs(Y - Yo).max() <= 2e-5 * max(1.0, np.abs(Yo).max())
+
+
+def test_backward_matches_oracle():
+    rl = _rl()
+    B = 333
+    net, p = _net_with_biases(rl, B, 21)
+    X = _inputs(22, B)
+    T = W.uniform(23, np.arange(B * 3)).reshape(B, 3) - 0.5
+    say("mlp backward B=%d" % B)
+    loss = net.grad(_cuda(X), _cuda(T))
+    g = net.get_grad().astype(np.float64)
+    lo, go = M.loss_and_grad(p.astype(np.float64), net.layer_shapes(), X, T)
+    assert loss == pytest.approx(lo, rel=2e-5)
+    assert np.abs(g - go).max() <= 2e-4 * np.abs(go).max()
+    # per layer as well, so that a small layer's error is not hidden by a large one
+    k = 0
+    for (o, i) in net.layer_shapes():
+        for n in (o * i, o):
+            seg = slice(k, k + n)
+            assert np.abs(g[seg] - go[seg]).max() <= 5e-4 * np.abs(go[seg]).max() + 1e-9, (o, i, n)
+            k += n
+
+
+def test_adam_matches_oracle_and_refreshes_bf16_weights():
+    rl = _rl()
+    B = 256
+    net, p = _net_with_biases(rl, B, 31)
+    X, T = _inputs(32, B), W.uniform(33, np.arange(B * 3)).reshape(B, 3) - 0.5
+    Xd, Td = _cuda(X), _cuda(T)
+    m = np.zeros(net.nparams)
+    v = np.zeros(net.nparams)
+    lr = 1e-3
+    for t in range(1, 4):
+        prev = net.get_params().astype(np.float64)
+        net.grad(Xd, Td)
+        g = net.get_grad().astype(np.float64)
+        net.adam_step(lr)
+        po, m, v = M.adam(prev, g, m, v, t, lr)
+        got = net.get_params().astype(np.float64)
+        assert np.abs(got - po).max() <= 1e-6 * np.abs(po).max() + 1e-4 * lr, t
+    # the forward pass now runs with the updated weights (rounded to bf16)
+    Y = net.forward(Xd).cpu().numpy().astype(np.float64)
+    Yo, _ = M.forward(net.get_params().astype(np.float64), net.layer_shapes(), X)
+    assert np.abs(Y - Yo).max() <= 2e-5 * max(1.0, np.abs(Yo).max())
+
+
+def _fp64_solver(rl, K=12, Np=3, N=2, nx=24, ny=16, steps=5, seed=0):
+    n, T, ux, uy = W.disc(nx, ny, 5, seed=seed)
+    s = rl.Solver(Np, K, N).init_fields(nx, ny, n, T, ux, uy, tau=0.8, dt=0.5, precision="f64")
+    s.step(steps)
+    return s
+
+
+def _oracle_site_stats(q, f):
+    nv, ny, nx = f.shape
+    out = np.zeros((ny * nx, 7))
+    for y in range(ny):
+        for x in range(nx):
+            out[y * nx + x] = O.site_stats(q.moments(f[:, y, x]))
+    return out
+
+
+def test_site_stats_match_oracle():
+    rl = _rl()
+    s = _fp64_solver(rl)
+    st = rl.site_stats(s).cpu().numpy().astype(np.float64)
+    ref = _oracle_site_stats(O.Quadrature(3, 12, 2), s.get_populations())
+    scale = np.abs(ref).max(axis=0)
+    assert np.all(np.abs(st[:, :7] - ref) <= 1e-6 * scale + 1e-7)
+    assert np.all(st[:, 7] == 0)
+
+
+def test_features_are_normalised_periodic_patches():
+    rl = _rl()
+    s = _fp64_solver(rl, nx=20, ny=9)
+    net = rl.MLP(max_batch=s.nx * s.ny)
+    mu = np.array([1.0, 2.0, 0.1, -0.1, 0.01, 0.0, -0.01])
+    sig = np.array([0.5, 0.25, 2.0, 3.0, 0.1, 0.2, 0.3])
+    net.set_norm(mu, sig, np.zeros(3), np.ones(3))
+    X = net.features(s).cpu().numpy().astype(np.float64)
+    st = rl.site_stats(s).cpu().numpy().astype(np.float64)[:, :7].reshape(s.ny, s.nx, 7)
+    ref = np.zeros((s.ny, s.nx, 64))
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            j = (dy + 1) * 3 + (dx + 1)
+            nb = np.roll(np.roll(st, -dy, axis=0), -dx, axis=1)   # value at (y + dy, x + dx)
+            ref[:, :, 7 * j:7 * j + 7] = (nb - mu) / sig
+    assert np.abs(X - ref.reshape(-1, 64)).max() <= 1e-5 * np.abs(ref).max()
+
+
+def _moment_change(q, f0, f1):
+    d = f1 - f0
+    nv, ny, nx = d.shape
+    return np.array([q.moments(d[:, y, x]) for y in range(ny) for x in range(nx)])
+
+
+def test_add_stress_changes_only_the_shear_stress():
+    rl = _rl()
+    s = _fp64_solver(rl)
+    q = O.Quadrature(3, 12, 2)
+    f0 = s.get_populations().copy()
+    S = s.nx * s.ny
+    d = (W.uniform(41, np.arange(S * 3)).reshape(S, 3) - 0.5) * 0.02
+    rl.add_stress(s, _cuda(d), 0.7)
+    dm = _moment_change(q, f0, s.get_populations())
+    d32 = d.astype(np.float32).astype(np.float64)
+    sc = float(np.float32(0.7))            # the scale crosses the boundary as a float
+    tol = 1e-13
+    assert np.abs(dm[:, :6]).max() <= tol                                   # N^mu, T^00, T^0i kept
+    assert np.abs(dm[:, 6] + dm[:, 8]).max() <= tol                         # trace T^xx + T^yy = T^00 kept
+    assert np.abs((dm[:, 6] - dm[:, 8]) - sc * (d32[:, 0] - d32[:, 2])).max() <= 1e-14
+    assert np.abs(dm[:, 7] - sc * d32[:, 1]).max() <= 1e-14
+
+
+def test_correct_increment_and_relaxation_forms():
+    rl = _rl()
+    s = _fp64_solver(rl)
+    q = O.Quadrature(3, 12, 2)
+    S = s.nx * s.ny
+    net = rl.MLP(max_batch=S)
+    p = np.zeros(net.nparams, dtype=np.float32)
+    b = np.array([0.5, -1.0, 0.25], dtype=np.float32)
+    p[-3:] = b                                         # constant normalised output
+    net.set_params(p)
+    omu, osig = np.array([1e-3, -2e-3, 3e-3]), np.array([4e-3, 5e-3, 6e-3])
+    net.set_norm(np.zeros(7), np.ones(7), omu, osig)
+    y = (omu.astype(np.float32) + osig.astype(np.float32) * b).astype(np.float64)
+    for relax in (False, True):
+        f0 = s.get_populations().copy()
+        pi = rl.site_stats(s).cpu().numpy().astype(np.float64)[:, 4:7]
+        net.correct(s, 0.5, relax=relax)
+        dm = _moment_change(q, f0, s.get_populations())
+        want = 0.5 * (y[None, :] - pi) if relax else np.broadcast_to(0.5 * y, (S, 3))
+        assert np.abs(dm[:, :6]).max() <= 1e-13
+        assert np.abs((dm[:, 6] - dm[:, 8]) - (want[:, 0] - want[:, 2])).max() <= 1e-8
+        assert np.abs(dm[:, 7] - want[:, 1]).max() <= 1e-8
+
+
+def test_resample_keeps_moments_and_odd_self_resample_is_identity():
+    rl = _rl()
+    n, T, ux, uy = W.quadrant(20, 14, seed=3)
+    fine = rl.Solver(3, 36, 2).init_fields(20, 14, n, T, ux, uy, tau=2.0, dt=0.5, precision="f64")
+    fine.step(6)
+    coarse = rl.Solver(3, 12, 2).init_fields(20, 14, n, T, ux, uy, tau=2.0, dt=0.5, precision="f64")
+    rl.resample(fine, coarse)
+    mf = _moment_change(O.Quadrature(3, 36, 2), np.zeros_like(fine.get_populations()), fine.get_populations())
+    mc = _moment_change(O.Quadrature(3, 12, 2), np.zeros_like(coarse.get_populations()), coarse.get_populations())
+    assert np.abs(mf - mc).max() <= 1e-12 * np.abs(mf).max()
+    a = rl.Solver(3, 13, 2).init_fields(20, 14, n, T, ux, uy, tau=2.0, dt=0.5, precision="f64")
+    a.step(4)
+    b = rl.Solver(3, 13, 2).init_fields(20, 14, n, T, ux, uy, tau=2.0, dt=0.5, precision="f64")
+    rl.resample(a, b)
+    assert np.abs(a.get_populations() - b.get_populations()).max() <= 1e-13 * np.abs(a.get_populations()).max()
+    with pytest.raises(rl.RlbmError):
+        rl.resample(a, rl.Solver(4, 13, 2).init_fields(20, 14, n, T, ux, uy, tau=2.0, dt=0.5, precision="f64"))
+
+
+def test_training_reduces_the_loss():
+    import torch
+    rl = _rl()
+    B = 2048
+    X = _inputs(51, 4 * B)
+    T = np.stack([np.sin(X[:, 0] + X[:, 5]), X[:, 1] * X[:, 2], np.tanh(X[:, 3] - X[:, 60])], 1)
+    Xd, Td = _cuda(X), _cuda(T)
+    net = rl.MLP(max_batch=B)
+    net.init_params(seed=52)
+    first = None
+    for it in range(300):
+        k = (it % 4) * B
+        loss = net.grad(Xd[k:k + B].contiguous(), Td[k:k + B].contiguous())
+        first = loss if first is None else first
+        net.adam_step(1e-3)
+    say("training loss %.4g -> %.4g" % (first, loss))
+    assert loss < first / 5
+
+
+def test_exact_stress_correction_reduces_coarse_error():
+    """The correction channel: a coarse run whose shear stress is set to the
+    fine run's after every step tracks the fine fields more closely than the
+    plain coarse run.  (This bounds what a learned correction of the stress
+    can gain; the network predicts this same quantity.)"""
+    rl = _rl()
+    from paper_2011_06856_amd import learned as Lr
+    side, Kc, Kf = 64, 16, 96
+    Kn, fld, tau, dt = Lr.shock(side, 10000)
+    steps = int(0.45 * side)
+    say("channel side=%d Kc=%d Kf=%d Kn=%.3g steps=%d" % (side, Kc, Kf, Kn, steps))
+    f = Lr.make_solver(Kf, side, fld, tau, dt)
+    c = Lr.make_solver(Kc, side, fld, tau, dt)
+    p = Lr.make_solver(Kc, side, fld, tau, dt)
+    for t in range(steps):
+        f.step(1)
+        c.step(1)
+        p.step(1)
+        gap = (rl.site_stats(f)[:, 4:7] - rl.site_stats(c)[:, 4:7]).contiguous()
+        rl.add_stress(c, gap)
+    ref = Lr.run_fields(f)
+    plain = Lr.rel_errors(Lr.run_fields(p), ref)
+    corr = Lr.rel_errors(Lr.run_fields(c), ref)
+    say("plain %s corrected %s" % (plain, corr))
+    assert corr["eps"] < 0.5 * plain["eps"]
+    assert corr["beta"] < 0.8 * plain["beta"]
