@@ -43,7 +43,7 @@ def counter_traffic(precision, side):
     return d.get("traffic_bytes")
 
 
-def gpu_run(cfg, steps, warmup, precision, waves):
+def gpu_run(cfg, steps, warmup, precision, waves, keep_fields=False):
     import torch
     from paper_2011_06856_amd import rlbm
     s = rlbm.Solver(cfg["Np"], cfg["K"], cfg["N"])
@@ -58,8 +58,11 @@ def gpu_run(cfg, steps, warmup, precision, waves):
     wall = time.perf_counter() - t0
     n, eps, ux, uy, ch = s.moments()
     ok = bool(np.isfinite(n).all() and np.isfinite(eps).all())
-    return dict(wall_s=wall, event_ms=ms_events, sv=float(cfg["nx"] * cfg["ny"] * s.nvel * steps),
-                waves=s.get_waves(), finite=ok, charges=ch.tolist())
+    out = dict(wall_s=wall, event_ms=ms_events, sv=float(cfg["nx"] * cfg["ny"] * s.nvel * steps),
+               waves=s.get_waves(), finite=ok, charges=ch.tolist())
+    if keep_fields:
+        out["fields"] = (n, eps, ux, uy)
+    return out
 
 
 def cpu_baseline(precision_unused, budget_s):
@@ -127,6 +130,56 @@ def batched_form(a):
     }
 
 
+def field_errors(a, ref):
+    """Per-field relative L2 and max errors of (n, eps, U^x, U^y) against a
+    reference; the velocity as beta = U^i / U^0."""
+    def beta(f):
+        g = np.sqrt(1 + f[2] ** 2 + f[3] ** 2)
+        return np.stack([f[2] / g, f[3] / g])
+    out = {}
+    for k, name in ((0, "n"), (1, "eps")):
+        out[name] = {"rel_l2": float(np.linalg.norm(a[k] - ref[k]) / np.linalg.norm(ref[k])),
+                     "rel_max": float(np.abs(a[k] - ref[k]).max() / np.abs(ref[k]).max())}
+    ba, br = beta(a), beta(ref)
+    out["beta"] = {"rel_l2": float(np.linalg.norm(ba - br) / np.linalg.norm(br)),
+                   "abs_max": float(np.abs(ba - br).max())}
+    return out
+
+
+def precision_form(a):
+    """Precision form: the quadrant Riemann problem at 2048^2 (periodic),
+    Np=6 x K=256 (1536 velocities), order 5, Kn=10.  FP32 populations timed;
+    the same steps in FP64 on the GPU give the per-field error of FP32."""
+    import torch
+    side = a.side if a.side != 1024 else 2048
+    cfg = W.quadrant_shock(side, steps=a.steps)
+    print("bench: precision form %s f32 steps=%d" % (cfg["name"], a.steps), file=sys.stderr, flush=True)
+    r32 = gpu_run(cfg, a.steps, a.warmup, "f32", a.waves, keep_fields=True)
+    torch.cuda.empty_cache()
+    print("bench: precision form f64 reference", file=sys.stderr, flush=True)
+    r64 = gpu_run(cfg, a.steps, a.warmup, "f64", 0, keep_fields=True)
+    torch.cuda.empty_cache()
+    launch_ms = r32["event_ms"] / a.steps
+    sv = r32["sv"]
+    achieved = BYTES_PER_SV["f32"] * sv / a.steps / (launch_ms * 1e-3) / 1e9
+    return {
+        "metric": METRIC, "value": sv / r32["wall_s"] / 1e9, "unit": "GSVUPS", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": 1e3 * r32["wall_s"] / a.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": cfg["name"] + "_order5", "grid": [side, side], "velocities": 1536, "order": 5,
+                   "waves_per_group": r32["waves"], "fields_finite": r32["finite"] and r64["finite"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_stream_collide",
+                     "algorithmic_bytes_per_sv": 8, "avg_launch_ms": launch_ms},
+        "fp64_reference": {"gsvups_events": sv / (r64["event_ms"] * 1e-3) / 1e9,
+                           "avg_launch_ms": r64["event_ms"] / a.steps},
+        "fp32_error_vs_fp64": field_errors(r32["fields"], r64["fields"]),
+        # global charges (sum N^0, T^00, T^0x, T^0y): FP32 minus FP64, relative to the FP64 sums of N^0 and T^00
+        "charges_fp32_minus_fp64": [float((x - y) / abs(r64["charges"][0 if i == 0 else 1]))
+                                    for i, (x, y) in enumerate(zip(r32["charges"], r64["charges"]))],
+    }
+
+
 def learned_form(a):
     """Learned form: 512^2 periodic shocks, Np=4; coarse K=24 plus the MLP
     stress correction against the plain solver swept over K in 24..384, all
@@ -157,7 +210,7 @@ def main():
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--form", default="plain", choices=["plain", "batched", "learned"])
+    ap.add_argument("--form", default="plain", choices=["plain", "batched", "learned", "precision"])
     ap.add_argument("--train-seeds", type=int, default=200, help="learned form: training seeds")
     ap.add_argument("--eval-seeds", type=int, default=20, help="learned form: held-out seeds")
     ap.add_argument("--epochs", type=int, default=10, help="learned form: training epochs")
@@ -171,6 +224,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if a.form == "batched":
         print(json.dumps(batched_form(a)), flush=True)
+        return
+    if a.form == "precision":
+        print(json.dumps(precision_form(a)), flush=True)
         return
     if a.form == "learned":
         print(json.dumps(learned_form(a)), flush=True)

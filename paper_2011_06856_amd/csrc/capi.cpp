@@ -124,6 +124,7 @@ SCParams make_params(rlbm_ctx c, int waves)
     p.bcx = c->bcx; p.bcy = c->bcy; p.S = c->S; p.rate = c->rate; p.flag = c->d_flag;
     const int chunk = (c->q.nvel + waves - 1) / waves;
     p.chunk = (chunk + RLBM_LB - 1) / RLBM_LB * RLBM_LB;
+    p.band = RLBM_BAND_DEFAULT;
     return p;
 }
 

@@ -53,8 +53,12 @@ __device__ __forceinline__ int wrap_idx(int i, int n, int bc)
 }
 
 // One work-group tile of the fused step (64 sites of one row, all
-// velocities); `tile` indexes the tiles of the grid row-major, smem is the
-// work-group's dynamic LDS.
+// velocities); smem is the work-group's dynamic LDS.  `tile` runs over bands
+// of P.band rows, and within a band down each column of tiles before the
+// next: consecutive tiles (those in flight together on one XCD) then form a
+// block a few tiles wide and P.band tall, so that the upwind row a tile reads
+// is read by its neighbour in the block at about the same time (L2 reuse even
+// when one grid row of all velocities exceeds the L2).
 template <typename TS, typename TC, int NM, int VPT>
 __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restrict__ fout,
                                         const SRec<TC>* srec_, const CRec<TC, NM>* crec_, const double* Gtab_,
@@ -82,8 +86,11 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
     TC* coef = part + NW * NMOM * 64;                   // [Np][NT][64]
 
     const int ntx = (P.nx + 63) >> 6;
-    const int ty = tile / ntx;
-    const int tx = tile - ty * ntx;
+    const int band = tile / (ntx * P.band);
+    const int r = tile - band * ntx * P.band;
+    const int bh = min(P.band, P.ny - band * P.band);
+    const int tx = r / bh;
+    const int ty = band * P.band + (r - tx * bh);
     const int x = tx * 64 + lane;
     const bool active = x < P.nx;
     const int xc = active ? x : P.nx - 1;
@@ -390,9 +397,13 @@ hipError_t launch_sc_t(int waves, const SCParams& p, hipStream_t st)
 // Held values per lane, by storage precision and order class: the register
 // budget (128 VGPRs at 16 waves per work-group) is shared with the FP64
 // coefficient evaluation, whose size grows with the order.
+#ifndef RLBM_VPT_F32_HI
+#define RLBM_VPT_F32_HI 48
+#endif
 template <typename TC, int NM>
 struct Vpt {
-    static constexpr int value = sizeof(TC) == 8 ? (NM <= 3 ? 32 : 16) : (NM <= 3 ? 64 : (NM <= 5 ? 48 : 32));
+    static constexpr int value =
+        sizeof(TC) == 8 ? (NM <= 3 ? 32 : 16) : (NM <= 3 ? 64 : (NM <= 5 ? RLBM_VPT_F32_HI : 32));
 };
 
 // Values held per lane by the persistent batch kernel.

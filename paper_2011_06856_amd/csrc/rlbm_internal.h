@@ -200,7 +200,12 @@ struct SCParams {
     double rate;           // dt / tau (0 for tau = inf)
     int* flag;
     int chunk;             // velocities per wave, a multiple of RLBM_LB
+    int band;              // tile order: rows per band (tiles run column by column within a band)
 };
+
+#ifndef RLBM_BAND_DEFAULT
+#define RLBM_BAND_DEFAULT 1
+#endif
 
 // One problem of a batch: its buffers, tables and step parameters, and the
 // index of its first work item.

@@ -1,7 +1,9 @@
 """Workload driver for rocprofv3 runs of the fused stream-and-collide kernel.
 
 Runs `--steps` steps of the circular-shock workload (side^2 periodic grid,
-Np=4 x K=64, order 3, Kn=0.01) at the given precision, then a device-to-device
+Np=4 x K=64, order 3, Kn=0.01) or, with `--workload quadrant`, of the
+quadrant Riemann problem (side^2, Np=6 x K=256, order 5, Kn=10) at the given
+precision, then a device-to-device
 copy of exactly `--copy-mib` MiB (read once, written once) whose FETCH_SIZE /
 WRITE_SIZE readings calibrate the counters to bytes.
 
@@ -25,13 +27,20 @@ def main():
     ap.add_argument("--side", type=int, default=1024)
     ap.add_argument("--Kn", type=float, default=0.01)
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--workload", default="circular", choices=["circular", "quadrant"])
+    ap.add_argument("--waves", type=int, default=0)
     a = ap.parse_args()
     import torch
     import workloads as W
     from paper_2011_06856_amd import rlbm
-    cfg = W.circular_shock(a.side, Kn=a.Kn, steps=a.steps)
+    if a.workload == "circular":
+        cfg = W.circular_shock(a.side, Kn=a.Kn, steps=a.steps)
+    else:
+        cfg = W.quadrant_shock(a.side, steps=a.steps)
     s = rlbm.Solver(cfg["Np"], cfg["K"], cfg["N"])
     s.init_fields(cfg["nx"], cfg["ny"], *cfg["fields"], tau=cfg["tau"], dt=cfg["dt"], precision=a.precision)
+    if a.waves:
+        s.set_waves(a.waves)
     s.step(a.steps)
     torch.cuda.synchronize()
     n = a.copy_mib * 1024 * 1024 // 4
