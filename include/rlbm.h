@@ -48,6 +48,7 @@ enum {
 
 enum { RLBM_F64 = 0, RLBM_F32 = 1, RLBM_BF16DEV = 2 };   /* population storage */
 enum { RLBM_BC_PERIODIC = 0, RLBM_BC_CLAMP = 1 };         /* per axis */
+enum { RLBM_KERNEL_AUTO = 0, RLBM_KERNEL_TILE = 1, RLBM_KERNEL_PUSH = 2 };   /* step kernel */
 
 /*
  * Build the quadrature of Sec. 2.3 (Eq. off-lattice-quad) on the host and
@@ -146,6 +147,24 @@ int rlbm_set_populations(rlbm_ctx ctx, const void* host, size_t bytes);
  * by the autotuner and by tile-shape tests.  RLBM_EINVAL if unsupported.
  */
 int rlbm_set_waves(rlbm_ctx ctx, int waves);
+
+/*
+ * Step kernel (Sec. 2.2, Eqs. streaming, interpolation, discrete_sum_moments,
+ * collision: the same step, two schedules):
+ *   RLBM_KERNEL_TILE  a work-group gathers, holds and reduces all streamed
+ *                     values of 64 sites before their collision;
+ *   RLBM_KERNEL_PUSH  each wave runs through all velocities of 64 sites once;
+ *                     its moments come from partial sums pushed by the
+ *                     previous step (13 slots x 8 moments per site, kept in
+ *                     two library-owned device buffers allocated on first
+ *                     use; recomputed after any external change of the
+ *                     populations);
+ *   RLBM_KERNEL_AUTO  (default) PUSH from 768 velocities on, else TILE.
+ * The results agree to rounding.  rlbm_get_kernel returns the kernel that
+ * rlbm_step uses.  RLBM_EINVAL for an unknown kind.
+ */
+int rlbm_set_kernel(rlbm_ctx ctx, int kind);
+int rlbm_get_kernel(rlbm_ctx ctx, int* kind);
 int rlbm_get_waves(rlbm_ctx ctx, int* waves);
 
 /* ------------------------------------------------------------------------ */

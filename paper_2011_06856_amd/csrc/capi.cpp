@@ -112,6 +112,14 @@ bool finite_arr(const double* a, long long S)
 
 }  // namespace
 
+// Automatic choice: the push kernel where a tile's streamed values would not
+// fit the register budget of the tile kernel (large velocity sets).
+int resolve_kernel(rlbm_ctx c)
+{
+    if (c->kern != RLBM_KERNEL_AUTO) return c->kern;
+    return c->q.nvel >= RLBM_PUSH_MIN_NVEL ? RLBM_KERNEL_PUSH : RLBM_KERNEL_TILE;
+}
+
 SCParams make_params(rlbm_ctx c, int waves)
 {
     SCParams p;
@@ -222,6 +230,7 @@ int rlbm_init_fields(rlbm_ctx c, int nx, int ny, const double* n, const double* 
 
     // device tables
     free_tables(c);
+    push_free(c);
     std::vector<VelRec<double>> vd;
     build_vel_table(c->q, dt, vd);
     const size_t nv = c->q.nvel;
@@ -286,6 +295,29 @@ int rlbm_step(rlbm_ctx c, int nsteps)
     if (!c) return RLBM_EINVAL;
     if (!c->have_fields) return fail(c, RLBM_ESTATE, "rlbm_step before rlbm_init_fields");
     if (nsteps < 0) return fail(c, RLBM_EINVAL, "nsteps < 0");
+    if (resolve_kernel(c) == RLBM_KERNEL_PUSH) {
+        if (!c->d_prec) {
+            std::string err;
+            const int rc = push_setup(c, err);
+            if (rc != RLBM_OK) {
+                push_free(c);
+                return fail(c, rc, "push kernel setup: " + err);
+            }
+        }
+        hipError_t e;
+        if (!c->pvalid && nsteps > 0) {
+            if ((e = launch_push(c, true)) != hipSuccess) return hip_fail(c, e, "push partial sums launch");
+            c->pvalid = 1;
+        }
+        for (int s = 0; s < nsteps; ++s) {
+            if ((e = launch_push(c, false)) != hipSuccess) return hip_fail(c, e, "push step launch");
+            c->cur ^= 1;
+            c->pcur ^= 1;
+            ++c->steps;
+        }
+        return RLBM_OK;
+    }
+    c->pvalid = 0;
     const int waves = c->waves ? c->waves : default_waves(c->prec, nmax_of(c->q.N), c->q.nvel);
     SCParams p = make_params(c, waves);
     for (int s = 0; s < nsteps; ++s) {
@@ -378,7 +410,25 @@ int rlbm_set_populations(rlbm_ctx c, const void* host, size_t bytes)
     if (!host || bytes != need) return fail(c, RLBM_EINVAL, "population buffer size mismatch");
     hipError_t e = hipStreamSynchronize(c->st);
     if (e == hipSuccess) e = hipMemcpy(c->f[c->cur], host, need, hipMemcpyHostToDevice);
+    c->pvalid = 0;
     return e == hipSuccess ? RLBM_OK : hip_fail(c, e, "set_populations");
+}
+
+int rlbm_set_kernel(rlbm_ctx c, int kind)
+{
+    if (!c) return RLBM_EINVAL;
+    if (kind != RLBM_KERNEL_AUTO && kind != RLBM_KERNEL_TILE && kind != RLBM_KERNEL_PUSH)
+        return fail(c, RLBM_EINVAL, "unknown kernel kind");
+    c->kern = kind;
+    c->pvalid = 0;
+    return RLBM_OK;
+}
+
+int rlbm_get_kernel(rlbm_ctx c, int* kind)
+{
+    if (!c || !kind) return RLBM_EINVAL;
+    *kind = resolve_kernel(c);
+    return RLBM_OK;
 }
 
 const char* rlbm_last_error(rlbm_ctx c)
@@ -392,6 +442,7 @@ int rlbm_destroy(rlbm_ctx c)
     if (!c) return RLBM_EINVAL;
     if (c->have_fields) (void)hipStreamSynchronize(c->st);
     free_tables(c);
+    push_free(c);
     if (c->ws_owned && c->ws) (void)hipFree(c->ws);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);

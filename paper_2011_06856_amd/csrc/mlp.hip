@@ -337,6 +337,7 @@ hipError_t forward(rlbm_mlp m, const float* X, int B, float* Y)
 // with Y de-normalised by (omu, osig) when they are given.
 int add_stress(rlbm_ctx c, const float* Y, const float* omu, const float* osig, const float* cur, float scale)
 {
+    c->pvalid = 0;   // the push kernel's partial sums no longer match the populations
     if (!c->d_corr) {
         std::vector<double> t(2 * (size_t)c->q.nvel);
         for (int v = 0; v < c->q.nvel; ++v) {
@@ -592,6 +593,7 @@ int rlbm_resample(rlbm_ctx src, rlbm_ctx dst)
     if ((src->prec != RLBM_F32 && src->prec != RLBM_F64) || (dst->prec != RLBM_F32 && dst->prec != RLBM_F64))
         return RLBM_EINVAL;
     const int Np = src->q.Np, Ks = src->q.K, Kd = dst->q.K, M = (std::min(Ks, Kd) - 1) / 2;
+    dst->pvalid = 0;
     std::vector<double> R((size_t)Np * Kd * Ks);
     for (int i = 0; i < Np; ++i)
         for (int j = 0; j < Kd; ++j)

@@ -1,0 +1,495 @@
+// push.hip -- the fused step for large velocity sets, with next-step moments
+// pushed forward instead of gathered.
+//
+// The tile kernel (kernels.hip) needs all streamed values of a site before
+// its collision, because the collision needs the site's moments (Eq.
+// discrete_sum_moments) and these need every velocity.  With 1536 velocities
+// one 64-site tile holds 393 KB of streamed values, most of a CU's register
+// file, so the load phase of one tile cannot overlap the collision phase of
+// another.  This kernel removes the dependency:
+//
+//   The moments that step t+1 will see at site y are a linear function of
+//   the populations step t writes: f*_v(y) is the bilinear combination of
+//   f_v at y, y - sx, y - sy, y - sx - sy (Eq. interpolation), so
+//     M_k(y) = sum_v P_k(v) f*_v(y) = sum over sources s and corners c of
+//              sum_{v with corner c at s} w_c(v) P_k(v) f_v(s).
+//   While a wave writes f_v(s) it accumulates these per-source partial sums
+//   (a centre slot and three displaced corners per quadrant of (sx, sy):
+//   13 slots x 8 moments per site) and stores them; the next step gathers
+//   its moments from the 13 slots of the 3x3 neighbourhood, with the same
+//   periodic or clamped index rules as the stream.
+//
+// A wave then owns 64 sites of one row and runs through all velocities once:
+// stream, equilibrium, relaxation, store and partial sums, with no
+// work-group barrier and no shared memory.  The velocities are grouped in
+// segments of one shell and one quadrant; inside a segment the bilinear
+// weights are ax = dt sx cos, ay = dt sy sin and the moment rows are p^a
+// times {1, cos, sin, cos^2, cos sin}, so the 32 weighted moment sums of a
+// segment follow from 9 angular monomial sums of f (9 FMAs per velocity).
+#include <cstring>
+#include <new>
+#include <type_traits>
+
+#include "rlbm_internal.h"
+
+#ifdef __HIP_DEVICE_COMPILE__
+#define PUSH_CONST_AS __attribute__((address_space(4)))
+#else
+#define PUSH_CONST_AS
+#endif
+
+namespace {
+
+// Per-velocity records of the push kernel, in segment order, in two tables
+// so that the loads of a whole batch can be addressed from a few scalar
+// registers before any arithmetic:
+// address record
+//   roff     byte offset of the velocity's input plane
+//   dx       byte shift to the upwind column, -sgn(cos th) * element size
+//   sy       upwind row sign as +-1
+struct alignas(16) PAddr {
+    long long roff;
+    int dx, sy;
+};
+// arithmetic record
+//   w[4]     bilinear weights (1-ax)(1-ay), ax(1-ay), (1-ax)ay, ax ay
+//   H[]      w_v {1, cos th, sin th, ..., cos NM th, sin NM th}
+//   cth sth  direction (collision frequency U^0 - U.n_v)
+//   mono[8]  c, s, c^2, c s, c^3, c^2 s, c^3 s, c^2 s^2 with c = cos th, s = sin th
+//   woff     byte offset of the velocity's output plane
+template <typename T, int NM>
+struct alignas(16) PRec {
+    T w[4];
+    T H[2 * NM + 1];
+    T cth, sth;
+    T mono[8];
+    long long woff;
+};
+
+// One segment: the velocities of shell i with upwind signs (sx, sy) of
+// quadrant q, padded with null records to whole load batches.
+struct PSeg {
+    int begin, nbatch;
+    double p;
+};
+
+struct PushParams {
+    const PAddr* paddr;      // PAddr[]
+    const void* prec;        // PRec<T, NM>[]
+    const PSeg* seg;         // [4][Np]
+    const double* G;
+    const double* Pc;
+    int nx, ny, Np, bcx, bcy, ntiles;
+    long long S;
+    double rate, dt;
+    int* flag;
+};
+
+constexpr int NSLOT = 13;   // centre + 3 displaced corners x 4 quadrants
+constexpr int NMOM = 8;     // N^0 N^x N^y T^00 T^0x T^0y T^xx T^xy
+
+// Quadrant q: upwind signs sx = +1 for q in {0, 1}, sy = +1 for q in {0, 3}.
+__host__ __device__ constexpr int qsx(int q) { return q < 2 ? 1 : -1; }
+__host__ __device__ constexpr int qsy(int q) { return (q == 0 || q == 3) ? 1 : -1; }
+
+__device__ __forceinline__ int wrapi(int i, int n, int bc)
+{
+    if (bc == RLBM_BC_PERIODIC) {
+        if (i < 0) i += n;
+        if (i >= n) i -= n;
+    } else {
+        i = i < 0 ? 0 : (i >= n ? n - 1 : i);
+    }
+    return i;
+}
+
+__device__ __forceinline__ int xcd_remap_p(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7, k = b & 7, j = b >> 3;
+    return k * q + min(k, r) + j;
+}
+
+// One wave-tile: 64 sites of row ty starting at column 64 tx.  INIT computes
+// only the partial sums of the current populations (no stream, no
+// collision, no population store).
+template <typename T, int NM, int LB, bool INIT>
+__device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ pin,
+                                          T* __restrict__ pout, const PushParams& P, int tile)
+{
+    constexpr int NT = 2 * NM + 1;
+    constexpr int GS = (RLBM_NMAX + 1) * (RLBM_NMAX + 1);
+    using CRec = const PUSH_CONST_AS PRec<T, NM>;
+    using CAddr = const PUSH_CONST_AS PAddr;
+    CAddr* const adr = (CAddr*)P.paddr;
+    using CSeg = const PUSH_CONST_AS PSeg;
+    using CDbl = const PUSH_CONST_AS double;
+    CRec* const rec = (CRec*)P.prec;
+    CSeg* const seg = (CSeg*)P.seg;
+    CDbl* const Gtab = (CDbl*)P.G;
+    CDbl* const Pc = (CDbl*)P.Pc;
+
+    const int lane = threadIdx.x & 63;
+    const int ntx = (P.nx + 63) >> 6;
+    const int ty = tile / ntx;
+    const int tx = tile - ty * ntx;
+    const int x = tx * 64 + lane;
+    const bool active = x < P.nx;
+    const int xc = active ? x : P.nx - 1;
+    const bool interior = tx > 0 && (tx + 1) * 64 < P.nx;
+    const long long S = P.S;
+    const int xm = wrapi(xc - 1, P.nx, P.bcx), xp = wrapi(xc + 1, P.nx, P.bcx);
+    const int ym = wrapi(ty - 1, P.ny, P.bcy), yp = wrapi(ty + 1, P.ny, P.bcy);
+    const long long site = (long long)ty * P.nx + xc;
+
+    // 1. moments of the streamed populations, gathered from the partial sums
+    //    pushed by the previous step (FP64 sum of the 13 contributions)
+    T a0 = T(0), ax = T(0), ay = T(0);
+    double fn_ = 0, fT = 0, fU0 = 0, fUx = 0, fUy = 0;
+    int ok = 0;
+    if (!INIT) {
+        // one moment at a time (13 loads in flight) so that the gather does
+        // not set the kernel's register peak
+        double mom[9];
+#pragma unroll 1
+        for (int k = 0; k < NMOM; ++k) {
+            double s = (double)pin[(long long)k * S + site];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int cx = qsx(q) > 0 ? xm : xp;     // column x - sx
+                const long long ry = (long long)(qsy(q) > 0 ? ym : yp) * P.nx;   // row y - sy
+                const T* b = pin + (long long)((1 + 3 * q) * NMOM + k) * S;
+                s += (double)b[(long long)ty * P.nx + cx];
+                s += (double)b[NMOM * S + ry + xc];
+                s += (double)b[2 * NMOM * S + ry + cx];
+            }
+            mom[k] = s;
+        }
+        mom[8] = mom[3] - mom[6];
+        const Frame fr = landau_frame(mom);
+        ok = fr.ok;
+        if (!fr.ok && active) atomicOr(P.flag, 1);
+        a0 = fr.ok ? (T)(P.rate * fr.U0) : T(0);
+        ax = fr.ok ? (T)(P.rate * fr.Ux) : T(0);
+        ay = fr.ok ? (T)(P.rate * fr.Uy) : T(0);
+        fn_ = fr.n; fT = fr.T; fU0 = fr.U0; fUx = fr.Ux; fUy = fr.Uy;
+    }
+
+    constexpr unsigned ES = sizeof(T);
+    const unsigned ocb = (unsigned)xc * ES;
+    const unsigned omb = (unsigned)xm * ES;
+    const unsigned opb = (unsigned)xp * ES;
+    const long long rowb = (long long)ty * P.nx * ES;
+    const long long dmb = (long long)ym * P.nx * ES - rowb;
+    const long long dpb = (long long)yp * P.nx * ES - rowb;
+    const char* const inb = reinterpret_cast<const char*>(fin) + rowb;
+    char* const outb = reinterpret_cast<char*>(fout) + rowb;
+    auto ld = [](const char* base, unsigned off) __attribute__((always_inline)) -> T {
+        return *reinterpret_cast<const T*>(base + off);
+    };
+
+    T cen[NMOM];
+#pragma unroll
+    for (int k = 0; k < NMOM; ++k) cen[k] = T(0);
+    const T dt = (T)P.dt;
+
+    // 2. the velocities, quadrant by quadrant and shell by shell; interior
+    //    tiles (FAST) reach the x neighbour by a scalar shift of the plane
+    //    offset and store without a lane mask
+    auto run = [&](auto fast) __attribute__((always_inline)) {
+        constexpr bool FAST = decltype(fast)::value;
+        for (int q = 0; q < 4; ++q) {
+            const T al = dt * (T)qsx(q), be = dt * (T)qsy(q), ga = al * be;
+            T acc[3][NMOM];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int k = 0; k < NMOM; ++k) acc[c][k] = T(0);
+            for (int i = 0; i < P.Np; ++i) {
+                CSeg& G = seg[q * P.Np + i];
+                T cc[NT];
+                if (!INIT) {
+                    shell_coeffs<NM>(Gtab + (size_t)i * GS, Pc, fn_, fT, fU0, fUx, fUy,
+                                     [&](int mm, double cm, double sm) __attribute__((always_inline)) {
+                                         if (!ok) cm = sm = 0.0;
+                                         if (mm == 0) {
+                                             cc[0] = (T)cm;
+                                         } else {
+                                             cc[2 * mm - 1] = (T)cm;
+                                             cc[2 * mm] = (T)sm;
+                                         }
+                                     });
+                }
+                T Sm[9];   // sum f, f c, f s, f c^2, f c s, f c^3, f c^2 s, f c^3 s, f c^2 s^2
+#pragma unroll
+                for (int j = 0; j < 9; ++j) Sm[j] = T(0);
+                const int v0 = G.begin;
+                for (int kb = 0; kb < G.nbatch; ++kb) {
+                    T raw[LB][4];
+#pragma unroll
+                    for (int b = 0; b < LB; ++b) {
+                        CAddr& R = adr[v0 + kb * LB + b];
+                        const char* p0 = inb + R.roff;
+                        if (INIT) {
+                            raw[b][0] = ld(p0, ocb);
+                        } else {
+                            const char* p1 = p0 + (R.sy > 0 ? dmb : dpb);
+                            if (FAST) {
+                                raw[b][0] = ld(p0, ocb); raw[b][1] = ld(p0 + R.dx, ocb);
+                                raw[b][2] = ld(p1, ocb); raw[b][3] = ld(p1 + R.dx, ocb);
+                            } else {
+                                const unsigned osb = R.dx < 0 ? omb : opb;
+                                raw[b][0] = ld(p0, ocb); raw[b][1] = ld(p0, osb);
+                                raw[b][2] = ld(p1, ocb); raw[b][3] = ld(p1, osb);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int b = 0; b < LB; ++b) {
+                        CRec& R = rec[v0 + kb * LB + b];
+                        T fnew;
+                        if (INIT) {
+                            // null records (zero equilibrium row) contribute nothing;
+                            // real ones exactly their value, as in the step
+                            fnew = R.H[0] != T(0) ? raw[b][0] : T(0);
+                        } else {
+                            const T f = R.w[0] * raw[b][0] + R.w[1] * raw[b][1] + R.w[2] * raw[b][2] +
+                                        R.w[3] * raw[b][3];
+                            T feq = cc[0] * R.H[0];
+#pragma unroll
+                            for (int t = 1; t < NT; ++t) feq += cc[t] * R.H[t];
+                            const T om = a0 - ax * R.cth - ay * R.sth;
+                            fnew = f + om * (feq - f);
+                            T* dst = reinterpret_cast<T*>(outb + R.woff + ocb);
+                            if (FAST || active) *dst = fnew;
+                        }
+                        Sm[0] += fnew;
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) Sm[1 + j] += fnew * R.mono[j];
+                    }
+                }
+                // fold the monomial sums into the weighted moment sums of the
+                // segment's four corners: with T_e = sum f e, the corner sums
+                // of e are C0 = T_e - al T_ce - be T_se + ga T_cse, C1 = al
+                // T_ce - ga T_cse, C2 = be T_se - ga T_cse, C3 = ga T_cse
+                const T S1 = Sm[0], Sc = Sm[1], Ss = Sm[2], Scc = Sm[3], Scs = Sm[4], Sccc = Sm[5], Sccs = Sm[6],
+                        Scccs = Sm[7], Sccss = Sm[8];
+                const T Sss = S1 - Scc, Scss = Sc - Sccc;
+                // (T, Tc, Ts, Tcs) of e = 1, c, s, c^2, c s
+                const T Te[5][4] = {{S1, Sc, Ss, Scs},
+                                    {Sc, Scc, Scs, Sccs},
+                                    {Ss, Scs, Sss, Scss},
+                                    {Scc, Sccc, Sccs, Scccs},
+                                    {Scs, Sccs, Scss, Sccss}};
+                const T p = (T)G.p, p2 = (T)(G.p * G.p);
+                // moment k: angular factor e(k), radial factor p or p^2
+                constexpr int EK[NMOM] = {0, 1, 2, 0, 1, 2, 3, 4};
+#pragma unroll
+                for (int k = 0; k < NMOM; ++k) {
+                    const T* t4 = Te[EK[k]];
+                    const T r = k < 3 ? p : p2;
+                    const T c3 = ga * t4[3];
+                    const T c1 = al * t4[1] - c3;
+                    const T c2 = be * t4[2] - c3;
+                    const T c0 = t4[0] - c1 - c2 - c3;
+                    cen[k] += r * c0;
+                    acc[0][k] += r * c1;
+                    acc[1][k] += r * c2;
+                    acc[2][k] += r * c3;
+                }
+            }
+            if (FAST || active) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int k = 0; k < NMOM; ++k)
+                        pout[(long long)((1 + 3 * q + c) * NMOM + k) * S + site] = acc[c][k];
+            }
+        }
+    };
+    if (interior)
+        run(std::true_type{});
+    else
+        run(std::false_type{});
+    if (interior || active) {
+#pragma unroll
+        for (int k = 0; k < NMOM; ++k) pout[(long long)k * S + site] = cen[k];
+    }
+}
+
+template <typename T, int NM, int LB, bool INIT>
+__global__ __launch_bounds__(256) void k_push_step(const T* __restrict__ fin, T* __restrict__ fout,
+                                                   const T* __restrict__ pin, T* __restrict__ pout, PushParams P)
+{
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
+    const int tile = xcd_remap_p(blockIdx.x, gridDim.x) * 4 + wv;
+    if (tile >= P.ntiles) return;   // whole waves
+    push_tile<T, NM, LB, INIT>(fin, fout, pin, pout, P, tile);
+}
+
+// Load batch per precision: FP64 holds half as many values per register.
+template <typename T>
+struct PushLB {
+    static constexpr int value = sizeof(T) == 8 ? 4 : 8;
+};
+
+template <typename T, int NM>
+hipError_t launch_push_t(bool init, const void* fin, void* fout, const void* pin, void* pout, const PushParams& P,
+                         hipStream_t st)
+{
+    constexpr int LB = PushLB<T>::value;
+    const unsigned blocks = (unsigned)((P.ntiles + 3) / 4);
+    if (init)
+        hipLaunchKernelGGL((k_push_step<T, NM, LB, true>), dim3(blocks), dim3(256), 0, st, (const T*)fin, (T*)fout,
+                           (const T*)pin, (T*)pout, P);
+    else
+        hipLaunchKernelGGL((k_push_step<T, NM, LB, false>), dim3(blocks), dim3(256), 0, st, (const T*)fin, (T*)fout,
+                           (const T*)pin, (T*)pout, P);
+    return hipGetLastError();
+}
+
+template <typename T, int NM>
+int upload_push_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, int precision, std::string& err)
+{
+    constexpr int LB = PushLB<T>::value;
+    const int Np = c->q.Np, K = c->q.K, nv = c->q.nvel;
+    const long long S = c->S, es = (long long)sizeof(T);
+    std::vector<PRec<T, NM>> recs;
+    std::vector<PAddr> adrs;
+    std::vector<PSeg> segs(4 * (size_t)Np);
+    PRec<T, NM> null;
+    std::memset(&null, 0, sizeof(null));
+    null.woff = (long long)nv * S * es;   // the spare plane
+    PAddr nulla;
+    std::memset(&nulla, 0, sizeof(nulla));
+    nulla.dx = -(int)es;
+    nulla.sy = 1;
+    for (int q = 0; q < 4; ++q)
+        for (int i = 0; i < Np; ++i) {
+            PSeg& G = segs[q * Np + i];
+            G.begin = (int)recs.size();
+            G.p = c->q.shell_p[i];
+            int count = 0;
+            for (int j = 0; j < K; ++j) {
+                const int v = i * K + j;
+                const VelRec<double>& R = vd[v];
+                if ((int)R.sx != qsx(q) || (int)R.sy != qsy(q)) continue;
+                PRec<T, NM> A;
+                std::memset(&A, 0, sizeof(A));
+                A.w[0] = (T)R.w00; A.w[1] = (T)R.w10; A.w[2] = (T)R.w01; A.w[3] = (T)R.w11;
+                for (int t = 0; t < 2 * NM + 1; ++t) A.H[t] = (T)R.H[t];
+                const double cs = R.cth, sn = R.sth;
+                A.cth = (T)cs; A.sth = (T)sn;
+                const double mono[8] = {cs, sn, cs * cs, cs * sn, cs * cs * cs, cs * cs * sn, cs * cs * cs * sn,
+                                        cs * cs * sn * sn};
+                for (int t = 0; t < 8; ++t) A.mono[t] = (T)mono[t];
+                A.woff = (long long)v * S * es;
+                PAddr D;
+                std::memset(&D, 0, sizeof(D));
+                D.roff = (long long)v * S * es;
+                D.dx = (R.sx > 0 ? -1 : 1) * (int)es;
+                D.sy = R.sy > 0 ? 1 : -1;
+                recs.push_back(A);
+                adrs.push_back(D);
+                ++count;
+            }
+            while (count % LB) {
+                recs.push_back(null);
+                adrs.push_back(nulla);
+                ++count;
+            }
+            G.nbatch = count / LB;
+        }
+    if ((long long)recs.size() > 4LL * nv + 4LL * Np * LB) {
+        err = "push table size";
+        return RLBM_EINVAL;
+    }
+    hipError_t e;
+    if ((e = hipMalloc(&c->d_prec, recs.size() * sizeof(PRec<T, NM>))) != hipSuccess) return RLBM_ENOMEM;
+    if ((e = hipMalloc(&c->d_paddr, adrs.size() * sizeof(PAddr))) != hipSuccess) return RLBM_ENOMEM;
+    if ((e = hipMemcpy(c->d_paddr, adrs.data(), adrs.size() * sizeof(PAddr), hipMemcpyHostToDevice)) != hipSuccess) {
+        err = hipGetErrorString(e);
+        return RLBM_EDEVICE;
+    }
+    if ((e = hipMalloc((void**)&c->d_pseg, segs.size() * sizeof(PSeg))) != hipSuccess) return RLBM_ENOMEM;
+    if ((e = hipMemcpy(c->d_prec, recs.data(), recs.size() * sizeof(PRec<T, NM>), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c->d_pseg, segs.data(), segs.size() * sizeof(PSeg), hipMemcpyHostToDevice)) != hipSuccess) {
+        err = hipGetErrorString(e);
+        return RLBM_EDEVICE;
+    }
+    const size_t pbytes = (size_t)NSLOT * NMOM * S * sizeof(T);
+    for (int b = 0; b < 2; ++b)
+        if ((e = hipMalloc(&c->pp[b], pbytes)) != hipSuccess) return RLBM_ENOMEM;
+    (void)precision;
+    return RLBM_OK;
+}
+
+}  // namespace
+
+// Drop the push kernel's tables and partial-sum buffers (capi.cpp calls it
+// when the grid or precision changes and at destroy).
+void push_free(rlbm_ctx c)
+{
+    if (c->d_prec) (void)hipFree(c->d_prec);
+    if (c->d_paddr) (void)hipFree(c->d_paddr);
+    if (c->d_pseg) (void)hipFree(c->d_pseg);
+    for (int b = 0; b < 2; ++b)
+        if (c->pp[b]) (void)hipFree(c->pp[b]);
+    c->d_prec = nullptr;
+    c->d_paddr = nullptr;
+    c->d_pseg = nullptr;
+    c->pp[0] = c->pp[1] = nullptr;
+    c->pvalid = 0;
+}
+
+// Build the push tables and buffers for the context's grid and precision.
+int push_setup(rlbm_ctx c, std::string& err)
+{
+    push_free(c);
+    std::vector<VelRec<double>> vd;
+    build_vel_table(c->q, c->dt, vd);
+    const int nm = nmax_of(c->q.N);
+    if (c->prec == RLBM_F32) {
+        if (nm == 3) return upload_push_t<float, 3>(c, vd, c->prec, err);
+        if (nm == 5) return upload_push_t<float, 5>(c, vd, c->prec, err);
+        return upload_push_t<float, 7>(c, vd, c->prec, err);
+    }
+    if (c->prec == RLBM_F64) {
+        if (nm == 3) return upload_push_t<double, 3>(c, vd, c->prec, err);
+        if (nm == 5) return upload_push_t<double, 5>(c, vd, c->prec, err);
+        return upload_push_t<double, 7>(c, vd, c->prec, err);
+    }
+    err = "the push kernel supports FP32 and FP64";
+    return RLBM_EINVAL;
+}
+
+// One launch of the push kernel: init = 1 recomputes the partial sums of
+// the current populations into pp[pcur]; init = 0 advances one step
+// (f[cur] -> f[cur^1], pp[pcur] -> pp[pcur^1]).
+hipError_t launch_push(rlbm_ctx c, bool init)
+{
+    PushParams P;
+    P.paddr = static_cast<const PAddr*>(c->d_paddr);
+    P.prec = c->d_prec;
+    P.seg = static_cast<const PSeg*>(c->d_pseg);
+    P.G = c->d_G;
+    P.Pc = c->d_Pc;
+    P.nx = c->nx; P.ny = c->ny; P.Np = c->q.Np; P.bcx = c->bcx; P.bcy = c->bcy;
+    P.ntiles = ((c->nx + 63) / 64) * c->ny;
+    P.S = c->S;
+    P.rate = c->rate;
+    P.dt = c->dt;
+    P.flag = c->d_flag;
+    const void* fin = c->f[c->cur];
+    void* fout = c->f[c->cur ^ 1];
+    const void* pin = c->pp[c->pcur];
+    void* pout = init ? c->pp[c->pcur] : c->pp[c->pcur ^ 1];
+    const int nm = nmax_of(c->q.N);
+    if (c->prec == RLBM_F32) {
+        if (nm == 3) return launch_push_t<float, 3>(init, fin, fout, pin, pout, P, c->st);
+        if (nm == 5) return launch_push_t<float, 5>(init, fin, fout, pin, pout, P, c->st);
+        return launch_push_t<float, 7>(init, fin, fout, pin, pout, P, c->st);
+    }
+    if (nm == 3) return launch_push_t<double, 3>(init, fin, fout, pin, pout, P, c->st);
+    if (nm == 5) return launch_push_t<double, 5>(init, fin, fout, pin, pout, P, c->st);
+    return launch_push_t<double, 7>(init, fin, fout, pin, pout, P, c->st);
+}

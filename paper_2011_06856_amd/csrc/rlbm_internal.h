@@ -203,6 +203,11 @@ struct SCParams {
     int band;              // tile order: rows per band (tiles run column by column within a band)
 };
 
+// Velocity count from which RLBM_KERNEL_AUTO selects the push kernel.
+#ifndef RLBM_PUSH_MIN_NVEL
+#define RLBM_PUSH_MIN_NVEL 768
+#endif
+
 #ifndef RLBM_BAND_DEFAULT
 #define RLBM_BAND_DEFAULT 1
 #endif
@@ -242,6 +247,15 @@ struct rlbm_ctx_s {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     long long steps = 0;
     double* d_corr = nullptr;            // learned correction: w p^2 {cos, sin} 2th per velocity
+    // push kernel (push.hip): segment-ordered velocity records, segments,
+    // double-buffered partial sums of the next step's moments
+    int kern = 0;                        // RLBM_KERNEL_AUTO / _TILE / _PUSH
+    void* d_prec = nullptr;
+    void* d_paddr = nullptr;
+    void* d_pseg = nullptr;
+    void* pp[2] = {nullptr, nullptr};
+    int pcur = 0;
+    int pvalid = 0;                      // pp[pcur] holds the partial sums of f[cur]
 };
 
 inline int nmax_of(int N) { return N <= 3 ? 3 : (N <= 5 ? 5 : 7); }
@@ -258,6 +272,13 @@ hipError_t launch_batch_step(int prec, int nmax, int waves, int grid, const Batc
                              int* counters, const int* bounds, int parity, const double* Pc, int max_np,
                              hipStream_t st);
 hipError_t launch_reset_counters(int* counters, hipStream_t st);
+
+// Push kernel (push.hip).
+void push_free(rlbm_ctx c);
+int push_setup(rlbm_ctx c, std::string& err);
+hipError_t launch_push(rlbm_ctx c, bool init);
+// Kernel used by rlbm_step for this context (resolves RLBM_KERNEL_AUTO).
+int resolve_kernel(rlbm_ctx c);
 int batch_grid(int prec, int nmax, int waves, int max_np);
 int default_waves(int prec, int nmax, int nvel);
 int max_vpt(int prec, int nmax);

@@ -40,6 +40,8 @@ SIGNATURES = [
     ("rlbm_set_populations", ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
     ("rlbm_set_waves", ctypes.c_int, [_vp, ctypes.c_int]),
     ("rlbm_get_waves", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
+    ("rlbm_set_kernel", ctypes.c_int, [_vp, ctypes.c_int]),
+    ("rlbm_get_kernel", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
     ("rlbm_host_feq", ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]),
     ("rlbm_host_landau", ctypes.c_int, [_dp, _dp]),
     ("rlbm_device_landau", ctypes.c_int, [ctypes.c_int, _dp, _dp]),
@@ -268,6 +270,18 @@ class Solver:
         w = ctypes.c_int()
         self._check(lib().rlbm_get_waves(self._h, ctypes.byref(w)))
         return w.value
+
+    KERNELS = {"auto": 0, "tile": 1, "push": 2}
+
+    def set_kernel(self, kind):
+        """Step kernel: "auto", "tile" or "push" (same step, two schedules)."""
+        self._check(lib().rlbm_set_kernel(self._h, self.KERNELS[kind]))
+        return self
+
+    def get_kernel(self):
+        k = ctypes.c_int()
+        self._check(lib().rlbm_get_kernel(self._h, ctypes.byref(k)))
+        return {v: n for n, v in self.KERNELS.items()}[k.value]
 
 
 class Batch:
