@@ -114,7 +114,7 @@ __device__ __forceinline__ int xcd_remap_p(int b, int nb)
 // collision, no population store).
 template <typename T, int NM, int LB, bool INIT>
 __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ pin,
-                                          T* __restrict__ pout, const PushParams& P, int tile)
+                                          T* __restrict__ pout, const PushParams& P, int tile, T* __restrict__ lacc)
 {
     constexpr int NT = 2 * NM + 1;
     constexpr int GS = (RLBM_NMAX + 1) * (RLBM_NMAX + 1);
@@ -187,9 +187,15 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
         return *reinterpret_cast<const T*>(base + off);
     };
 
-    T cen[NMOM];
+    // The 32 weighted moment sums of the current quadrant (centre slot and
+    // three displaced corners) are touched once per segment: they live in
+    // this wave's LDS (lane-contiguous, [slot][k][64]), not in registers.
+    // lacc[c][k]: c = 0 centre (all quadrants), 1..3 the quadrant's corners.
+    auto L = [&](int c, int k) __attribute__((always_inline)) -> T& { return lacc[(c * NMOM + k) * 64 + lane]; };
 #pragma unroll
-    for (int k = 0; k < NMOM; ++k) cen[k] = T(0);
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int k = 0; k < NMOM; ++k) L(c, k) = T(0);
     const T dt = (T)P.dt;
 
     // 2. the velocities, quadrant by quadrant and shell by shell; interior
@@ -199,11 +205,6 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
         constexpr bool FAST = decltype(fast)::value;
         for (int q = 0; q < 4; ++q) {
             const T al = dt * (T)qsx(q), be = dt * (T)qsy(q), ga = al * be;
-            T acc[3][NMOM];
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int k = 0; k < NMOM; ++k) acc[c][k] = T(0);
             for (int i = 0; i < P.Np; ++i) {
                 CSeg& G = seg[q * P.Np + i];
                 T cc[NT];
@@ -224,6 +225,7 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
                 for (int j = 0; j < 9; ++j) Sm[j] = T(0);
                 const int v0 = G.begin;
                 for (int kb = 0; kb < G.nbatch; ++kb) {
+                    // LB velocities' loads in flight, then their arithmetic
                     T raw[LB][4];
 #pragma unroll
                     for (int b = 0; b < LB; ++b) {
@@ -291,19 +293,19 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
                     const T c1 = al * t4[1] - c3;
                     const T c2 = be * t4[2] - c3;
                     const T c0 = t4[0] - c1 - c2 - c3;
-                    cen[k] += r * c0;
-                    acc[0][k] += r * c1;
-                    acc[1][k] += r * c2;
-                    acc[2][k] += r * c3;
+                    L(0, k) += r * c0;
+                    L(1, k) += r * c1;
+                    L(2, k) += r * c2;
+                    L(3, k) += r * c3;
                 }
             }
-            if (FAST || active) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c)
+            for (int c = 0; c < 3; ++c)
 #pragma unroll
-                    for (int k = 0; k < NMOM; ++k)
-                        pout[(long long)((1 + 3 * q + c) * NMOM + k) * S + site] = acc[c][k];
-            }
+                for (int k = 0; k < NMOM; ++k) {
+                    if (FAST || active) pout[(long long)((1 + 3 * q + c) * NMOM + k) * S + site] = L(1 + c, k);
+                    L(1 + c, k) = T(0);
+                }
         }
     };
     if (interior)
@@ -312,24 +314,41 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
         run(std::false_type{});
     if (interior || active) {
 #pragma unroll
-        for (int k = 0; k < NMOM; ++k) pout[(long long)k * S + site] = cen[k];
+        for (int k = 0; k < NMOM; ++k) pout[(long long)k * S + site] = L(0, k);
     }
 }
 
+#ifndef RLBM_PUSH_WPE
+#define RLBM_PUSH_WPE 1
+#endif
+#ifndef RLBM_PUSH_LB_F32
+#define RLBM_PUSH_LB_F32 8
+#endif
+
 template <typename T, int NM, int LB, bool INIT>
-__global__ __launch_bounds__(256) void k_push_step(const T* __restrict__ fin, T* __restrict__ fout,
+__global__ __launch_bounds__(256, RLBM_PUSH_WPE) void k_push_step(const T* __restrict__ fin, T* __restrict__ fout,
                                                    const T* __restrict__ pin, T* __restrict__ pout, PushParams P)
 {
+    extern __shared__ __align__(16) unsigned char psmem[];
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
-    const int tile = xcd_remap_p(blockIdx.x, gridDim.x) * 4 + wv;
-    if (tile >= P.ntiles) return;   // whole waves
-    push_tile<T, NM, LB, INIT>(fin, fout, pin, pout, P, tile);
+    // A work-group's 4 waves take the same 64 columns of 4 consecutive rows:
+    // they run through the velocities side by side, so the upwind row one
+    // wave reads is the row its neighbour reads at about the same time (L1/L2
+    // reuse; one grid row of all velocities is far larger than the L2).
+    const int ntx = (P.nx + 63) >> 6;
+    const int b = xcd_remap_p(blockIdx.x, gridDim.x);
+    const int band = b / ntx;
+    const int ty = band * 4 + wv;
+    if (ty >= P.ny) return;   // whole waves; no barrier follows
+    const int tile = ty * ntx + (b - band * ntx);
+    T* lacc = reinterpret_cast<T*>(psmem) + (size_t)wv * 4 * NMOM * 64;
+    push_tile<T, NM, LB, INIT>(fin, fout, pin, pout, P, tile, lacc);
 }
 
 // Load batch per precision: FP64 holds half as many values per register.
 template <typename T>
 struct PushLB {
-    static constexpr int value = sizeof(T) == 8 ? 4 : 8;
+    static constexpr int value = sizeof(T) == 8 ? 4 : RLBM_PUSH_LB_F32;
 };
 
 template <typename T, int NM>
@@ -337,12 +356,13 @@ hipError_t launch_push_t(bool init, const void* fin, void* fout, const void* pin
                          hipStream_t st)
 {
     constexpr int LB = PushLB<T>::value;
-    const unsigned blocks = (unsigned)((P.ntiles + 3) / 4);
+    const unsigned blocks = (unsigned)(((P.nx + 63) / 64) * ((P.ny + 3) / 4));
+    const size_t lds = (size_t)4 * 4 * NMOM * 64 * sizeof(T);   // 4 waves x 32 sums x 64 lanes
     if (init)
-        hipLaunchKernelGGL((k_push_step<T, NM, LB, true>), dim3(blocks), dim3(256), 0, st, (const T*)fin, (T*)fout,
+        hipLaunchKernelGGL((k_push_step<T, NM, LB, true>), dim3(blocks), dim3(256), lds, st, (const T*)fin, (T*)fout,
                            (const T*)pin, (T*)pout, P);
     else
-        hipLaunchKernelGGL((k_push_step<T, NM, LB, false>), dim3(blocks), dim3(256), 0, st, (const T*)fin, (T*)fout,
+        hipLaunchKernelGGL((k_push_step<T, NM, LB, false>), dim3(blocks), dim3(256), lds, st, (const T*)fin, (T*)fout,
                            (const T*)pin, (T*)pout, P);
     return hipGetLastError();
 }
