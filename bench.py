@@ -30,10 +30,10 @@ METRIC = "GSVUPS + % HBM roofline; coarse-angle+MLP vs fine-angle speedup at equ
 BYTES_PER_SV = {"f32": 8, "f64": 16}
 
 
-def counter_traffic(precision, side):
-    """HBM bytes per launch from the committed rocprofv3 counter summary of
-    this kernel and workload, or None if absent or taken on other sources."""
-    path = os.path.join(ROOT, "profiles", "stream_collide_%s_circular_%d.json" % (precision, side))
+def counter_traffic(name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    profiles/<name>.json, or None if absent or taken on other sources."""
+    path = os.path.join(ROOT, "profiles", name + ".json")
     if not os.path.exists(path):
         return None
     from paper_2011_06856_amd.profile_summary import kernel_source_hash
@@ -59,7 +59,7 @@ def gpu_run(cfg, steps, warmup, precision, waves, keep_fields=False):
     n, eps, ux, uy, ch = s.moments()
     ok = bool(np.isfinite(n).all() and np.isfinite(eps).all())
     out = dict(wall_s=wall, event_ms=ms_events, sv=float(cfg["nx"] * cfg["ny"] * s.nvel * steps),
-               waves=s.get_waves(), finite=ok, charges=ch.tolist())
+               waves=s.get_waves(), kernel=s.get_kernel(), finite=ok, charges=ch.tolist())
     if keep_fields:
         out["fields"] = (n, eps, ux, uy)
     return out
@@ -167,9 +167,11 @@ def precision_form(a):
         "warmup": a.warmup, "ms_per_step": 1e3 * r32["wall_s"] / a.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": cfg["name"] + "_order5", "grid": [side, side], "velocities": 1536, "order": 5,
-                   "waves_per_group": r32["waves"], "fields_finite": r32["finite"] and r64["finite"]},
+                   "kernel": r32["kernel"], "fields_finite": r32["finite"] and r64["finite"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_stream_collide",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": counter_traffic("push_step_f32_quadrant_%d" % side) if r32["kernel"] == "push" else None,
+                     "kernel": "k_push_step" if r32["kernel"] == "push" else "k_stream_collide",
                      "algorithmic_bytes_per_sv": 8, "avg_launch_ms": launch_ms},
         "fp64_reference": {"gsvups_events": sv / (r64["event_ms"] * 1e-3) / 1e9,
                            "avg_launch_ms": r64["event_ms"] / a.steps},
@@ -258,10 +260,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": "circular_shock_%d_np4_k64_order3" % a.side, "grid": [a.side, a.side],
                    "velocities": 256, "Kn": [0.01, 1.0], "runs": 2, "steps_per_run": a.steps,
-                   "waves_per_group": runs[0.01]["waves"], "fields_finite": all(r["finite"] for r in runs.values())},
+                   "kernel": runs[0.01]["kernel"], "waves_per_group": runs[0.01]["waves"],
+                   "fields_finite": all(r["finite"] for r in runs.values())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(a.precision, a.side),
-                     "kernel": "k_stream_collide", "algorithmic_bytes_per_sv": BYTES_PER_SV[a.precision],
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic("stream_collide_%s_circular_%d" % (a.precision, a.side)),
+                     "kernel": "k_stream_collide" if runs[0.01]["kernel"] == "tile" else "k_push_step",
+                     "algorithmic_bytes_per_sv": BYTES_PER_SV[a.precision],
                      "avg_launch_ms": launch_ms},
     }
     if not a.no_cpu_baseline:

@@ -218,7 +218,8 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
         const TC om_ = a0 - ax * R.cth - ay * R.sth;
         const TC fn = f + om_ * (feq - f);
         TS* dst = reinterpret_cast<TS*>(outb + R.woff + ocb);
-#ifdef RLBM_NT_STORE
+        // non-temporal: the next read of this plane is a step away
+#ifndef RLBM_TEMPORAL_STORE
         if (decltype(fast)::value || active) __builtin_nontemporal_store((TS)fn, dst);
 #else
         if (decltype(fast)::value || active) *dst = (TS)fn;
@@ -400,10 +401,13 @@ hipError_t launch_sc_t(int waves, const SCParams& p, hipStream_t st)
 #ifndef RLBM_VPT_F32_HI
 #define RLBM_VPT_F32_HI 48
 #endif
+#ifndef RLBM_VPT_F32_LO
+#define RLBM_VPT_F32_LO 64
+#endif
 template <typename TC, int NM>
 struct Vpt {
     static constexpr int value =
-        sizeof(TC) == 8 ? (NM <= 3 ? 32 : 16) : (NM <= 3 ? 64 : (NM <= 5 ? RLBM_VPT_F32_HI : 32));
+        sizeof(TC) == 8 ? (NM <= 3 ? 32 : 16) : (NM <= 3 ? RLBM_VPT_F32_LO : (NM <= 5 ? RLBM_VPT_F32_HI : 32));
 };
 
 // Values held per lane by the persistent batch kernel.

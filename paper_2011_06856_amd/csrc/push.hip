@@ -56,7 +56,7 @@ struct alignas(16) PAddr {
 //   H[]      w_v {1, cos th, sin th, ..., cos NM th, sin NM th}
 //   cth sth  direction (collision frequency U^0 - U.n_v)
 //   mono[8]  c, s, c^2, c s, c^3, c^2 s, c^3 s, c^2 s^2 with c = cos th, s = sin th
-//   woff     byte offset of the velocity's output plane
+//   woff     byte offset of the velocity's output plane (padding: the spare plane)
 template <typename T, int NM>
 struct alignas(16) PRec {
     T w[4];
@@ -261,8 +261,13 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
                             for (int t = 1; t < NT; ++t) feq += cc[t] * R.H[t];
                             const T om = a0 - ax * R.cth - ay * R.sth;
                             fnew = f + om * (feq - f);
+                            // non-temporal: the next read of this plane is a step away
                             T* dst = reinterpret_cast<T*>(outb + R.woff + ocb);
+#ifndef RLBM_TEMPORAL_STORE
+                            if (FAST || active) __builtin_nontemporal_store(fnew, dst);
+#else
                             if (FAST || active) *dst = fnew;
+#endif
                         }
                         Sm[0] += fnew;
 #pragma unroll
@@ -376,13 +381,12 @@ int upload_push_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, int precisi
     std::vector<PRec<T, NM>> recs;
     std::vector<PAddr> adrs;
     std::vector<PSeg> segs(4 * (size_t)Np);
+    // padding records: zero weights and equilibrium row, a store to the
+    // spare plane, loads from the plane of the record before them (cache
+    // hits, no extra HBM reads)
     PRec<T, NM> null;
     std::memset(&null, 0, sizeof(null));
-    null.woff = (long long)nv * S * es;   // the spare plane
-    PAddr nulla;
-    std::memset(&nulla, 0, sizeof(nulla));
-    nulla.dx = -(int)es;
-    nulla.sy = 1;
+    null.woff = (long long)nv * S * es;
     for (int q = 0; q < 4; ++q)
         for (int i = 0; i < Np; ++i) {
             PSeg& G = segs[q * Np + i];
@@ -413,6 +417,14 @@ int upload_push_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, int precisi
                 ++count;
             }
             while (count % LB) {
+                PAddr nulla;
+                std::memset(&nulla, 0, sizeof(nulla));
+                if (!adrs.empty()) {
+                    nulla = adrs.back();
+                } else {
+                    nulla.dx = -(int)es;
+                    nulla.sy = 1;
+                }
                 recs.push_back(null);
                 adrs.push_back(nulla);
                 ++count;

@@ -1,0 +1,30 @@
+#!/bin/bash
+# rocprofv3 summaries of the two step kernels on their benchmark workloads:
+#   k_stream_collide  circular shock 1024^2, 256 velocities, FP32 (tile kernel)
+#   k_push_step       quadrant problem 2048^2, 1536 velocities, order 5, FP32 (push kernel)
+# Per workload: a kernel-trace/stats run, then a FETCH_SIZE run and a WRITE_SIZE
+# run (counters in passes of their own), each ending with a 1 GiB device copy
+# that calibrates the counters to bytes.  Run from the repository root on a
+# GPU machine:  bash paper_2011_06856_amd/profile_all.sh OUT_DIR
+# Writes OUT_DIR/raw/... (rocprofv3 CSV) and OUT_DIR/<name>.md/.json.
+set -e
+OUT=${1:-gpurun_out/profiles}
+ROOT=$(pwd)
+export TMPDIR=/tmp
+run() {   # name, kernel, launch bytes, stats args, counter args
+    local name=$1 kernel=$2 bytes=$3 sargs=$4 cargs=$5
+    local D=$OUT/raw/$name
+    timeout -s KILL 180 rocprofv3 --kernel-trace --stats -d $D/stats -o run --output-format csv -- \
+        python3 -m paper_2011_06856_amd.profile_run $sargs
+    timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE -d $D/fetch -o run --output-format csv -- \
+        python3 -m paper_2011_06856_amd.profile_run $cargs
+    timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -d $D/write -o run --output-format csv -- \
+        python3 -m paper_2011_06856_amd.profile_run $cargs
+    python3 -m paper_2011_06856_amd.profile_summary --stats $D/stats --fetch $D/fetch --write $D/write \
+        --name $name --kernel "$kernel" --launch-bytes $bytes --out-dir $OUT \
+        --command "rocprofv3 --kernel-trace --stats -- python3 -m paper_2011_06856_amd.profile_run $sargs ; rocprofv3 --pmc FETCH_SIZE -- python3 -m paper_2011_06856_amd.profile_run $cargs ; rocprofv3 --pmc WRITE_SIZE -- python3 -m paper_2011_06856_amd.profile_run $cargs (bash paper_2011_06856_amd/profile_all.sh)"
+}
+# algorithmic bytes per launch: 8 B per site-velocity (FP32 read + write)
+run stream_collide_f32_circular_1024 "k_stream_collide<float, float, 3, 64>" 2147483648 "--steps 20" "--steps 4"
+run push_step_f32_quadrant_2048 "k_push_step<float, 5, 8, false>" 51539607552 \
+    "--workload quadrant --side 2048 --steps 6" "--workload quadrant --side 2048 --steps 3"

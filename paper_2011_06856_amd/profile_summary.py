@@ -19,7 +19,8 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "rlbm_internal.h")]
+KERNEL_SOURCES = sorted(os.path.join(HERE, "csrc", f) for f in os.listdir(os.path.join(HERE, "csrc"))
+                        if f.endswith((".hip", ".h", ".cpp")))
 
 
 def kernel_source_hash():
@@ -56,6 +57,7 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--kernel", default="k_stream_collide")
     ap.add_argument("--launch-bytes", type=float, required=True, help="algorithmic bytes per launch")
+    ap.add_argument("--out-dir", default=os.path.join(ROOT, "profiles"))
     a = ap.parse_args()
 
     stats = _rows(a.stats, "kernel_stats.csv")
@@ -64,7 +66,7 @@ def main():
     copy_kib = a.copy_mib * 1024.0
 
     def pick(d, key):
-        vals = [v for k, vs in d.items() if key in k for v in vs]
+        vals = [v for k, vs in d.items() if key in k.replace("(anonymous namespace)::", "") for v in vs]
         return vals
 
     kf, kw = pick(fetch, a.kernel), pick(write, a.kernel)
@@ -76,7 +78,7 @@ def main():
     traffic = None
     if kf_avg and kw_avg and f_fac and w_fac:
         traffic = (kf_avg * f_fac + kw_avg * w_fac) * 1024.0
-    kstat = [r for r in stats if a.kernel in r["Name"]]
+    kstat = [r for r in stats if a.kernel in r["Name"].replace("(anonymous namespace)::", "")]
     avg_ns = float(kstat[0]["AverageNs"]) if kstat else None
 
     lines = ["# %s" % a.name, "",
@@ -101,13 +103,13 @@ def main():
               "| avg launch duration | %s us |" % ("%.1f" % (avg_ns / 1e3) if avg_ns else "n/a"),
               "| algorithmic GB/s at that duration | %s |" % ("%.0f" % (a.launch_bytes / avg_ns) if avg_ns else "n/a"),
               "", "Kernel sources sha256: `%s`" % kernel_source_hash(), ""]
-    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    md = os.path.join(ROOT, "profiles", a.name + ".md")
+    os.makedirs(a.out_dir, exist_ok=True)
+    md = os.path.join(a.out_dir, a.name + ".md")
     open(md, "w").write("\n".join(lines))
     js = dict(name=a.name, command=a.command, kernel=a.kernel, avg_launch_ns=avg_ns, traffic_bytes=traffic,
               fetch_kib=kf_avg, write_kib=kw_avg, fetch_factor=f_fac, write_factor=w_fac,
               launch_bytes=a.launch_bytes, kernel_sha256=kernel_source_hash())
-    json.dump(js, open(os.path.join(ROOT, "profiles", a.name + ".json"), "w"), indent=1)
+    json.dump(js, open(os.path.join(a.out_dir, a.name + ".json"), "w"), indent=1)
     print(md)
 
 
