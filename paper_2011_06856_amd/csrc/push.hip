@@ -38,6 +38,11 @@
 #define PUSH_CONST_AS
 #endif
 
+// Work-group barrier every RLBM_PUSH_SYNC load batches (0: none).
+#ifndef RLBM_PUSH_SYNC
+#define RLBM_PUSH_SYNC 0
+#endif
+
 namespace {
 
 // Per-velocity records of the push kernel, in segment order, in two tables
@@ -114,7 +119,8 @@ __device__ __forceinline__ int xcd_remap_p(int b, int nb)
 // collision, no population store).
 template <typename T, int NM, int LB, bool INIT>
 __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ pin,
-                                          T* __restrict__ pout, const PushParams& P, int tile, T* __restrict__ lacc)
+                                          T* __restrict__ pout, const PushParams& P, int tile, T* __restrict__ lacc,
+                                          bool live)
 {
     constexpr int NT = 2 * NM + 1;
     constexpr int GS = (RLBM_NMAX + 1) * (RLBM_NMAX + 1);
@@ -133,9 +139,9 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
     const int ty = tile / ntx;
     const int tx = tile - ty * ntx;
     const int x = tx * 64 + lane;
-    const bool active = x < P.nx;
-    const int xc = active ? x : P.nx - 1;
-    const bool interior = tx > 0 && (tx + 1) * 64 < P.nx;
+    const bool active = x < P.nx && live;
+    const int xc = x < P.nx ? x : P.nx - 1;
+    const bool interior = tx > 0 && (tx + 1) * 64 < P.nx && live;
     const long long S = P.S;
     const int xm = wrapi(xc - 1, P.nx, P.bcx), xp = wrapi(xc + 1, P.nx, P.bcx);
     const int ym = wrapi(ty - 1, P.ny, P.bcy), yp = wrapi(ty + 1, P.ny, P.bcy);
@@ -273,6 +279,11 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
 #pragma unroll
                         for (int j = 0; j < 8; ++j) Sm[1 + j] += fnew * R.mono[j];
                     }
+#if RLBM_PUSH_SYNC
+                    // keep the work-group's 4 row-waves within a few batches of
+                    // each other, so that the rows they share are fetched once
+                    if (!INIT && (kb % RLBM_PUSH_SYNC) == RLBM_PUSH_SYNC - 1) __syncthreads();
+#endif
                 }
                 // fold the monomial sums into the weighted moment sums of the
                 // segment's four corners: with T_e = sum f e, the corner sums
@@ -344,10 +355,18 @@ __global__ __launch_bounds__(256, RLBM_PUSH_WPE) void k_push_step(const T* __res
     const int b = xcd_remap_p(blockIdx.x, gridDim.x);
     const int band = b / ntx;
     const int ty = band * 4 + wv;
+#if RLBM_PUSH_SYNC
+    // rows past the grid (last band) run the same loop on the last row with
+    // every store off, so that all waves meet the same barriers
+    const bool live = ty < P.ny;
+    const int tile = (live ? ty : P.ny - 1) * ntx + (b - band * ntx);
+#else
     if (ty >= P.ny) return;   // whole waves; no barrier follows
+    const bool live = true;
     const int tile = ty * ntx + (b - band * ntx);
+#endif
     T* lacc = reinterpret_cast<T*>(psmem) + (size_t)wv * 4 * NMOM * 64;
-    push_tile<T, NM, LB, INIT>(fin, fout, pin, pout, P, tile, lacc);
+    push_tile<T, NM, LB, INIT>(fin, fout, pin, pout, P, tile, lacc, live);
 }
 
 // Load batch per precision: FP64 holds half as many values per register.
