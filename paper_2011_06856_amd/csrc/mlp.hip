@@ -81,6 +81,59 @@ __global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ A, const
         }
 }
 
+// The same product on the matrix cores: 64x64 output tile per 256-thread
+// work-group, one 32x32 quadrant per wave, v_mfma_f32_32x32x2f32 (FP32
+// operands, FP32 accumulate; bfloat16 weights are widened exactly), K in
+// steps of 16 staged through LDS.  Operand layout of the instruction: lane l
+// supplies A[l % 32][k0 + l / 32] and B[k0 + l / 32][l % 32]; accumulator
+// register r of lane l is C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+template <bool TA, bool TB, typename TBt>
+__global__ __launch_bounds__(256) void k_gemm_mfma(const float* __restrict__ A, const TBt* __restrict__ B,
+                                                   float* __restrict__ C, int M, int N, int K, int accumulate)
+{
+    __shared__ float As[16][64 + 4];
+    __shared__ float Bs[16][64 + 4];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    floatx16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        for (int e = tid; e < 16 * 64; e += 256) {
+            const int kk = e / 64, mm = e % 64;
+            const int gm = m0 + mm, gk = k0 + kk;
+            float va = 0.f;
+            if (gm < M && gk < K) va = TA ? A[(long)gk * M + gm] : A[(long)gm * K + gk];
+            As[kk][mm] = va;
+            const int gn = n0 + mm;
+            float vb = 0.f;
+            if (gn < N && gk < K) vb = TB ? ld_w(B, (long)gn * K + gk) : ld_w(B, (long)gk * N + gn);
+            Bs[kk][mm] = vb;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 2) {
+            const float a = As[kk + (lane >> 5)][wm + (lane & 31)];
+            const float b = Bs[kk + (lane >> 5)][wn + (lane & 31)];
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int gm = m0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int gn = n0 + wn + (lane & 31);
+        if (gm < M && gn < N) {
+            float* c = C + (long)gm * N + gn;
+            *c = accumulate ? *c + acc[r] : acc[r];
+        }
+    }
+}
+
 __device__ inline float gelu(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
 __device__ inline float gelu_d(float x)
 {
@@ -307,7 +360,11 @@ template <bool TA, bool TB, typename TBt>
 hipError_t gemm(hipStream_t st, const float* A, const TBt* B, float* C, int M, int N, int K, int acc)
 {
     dim3 grid((N + 63) / 64, (M + 63) / 64);
+#ifdef RLBM_MLP_VALU_GEMM
     hipLaunchKernelGGL((k_gemm<TA, TB, TBt>), grid, dim3(256), 0, st, A, B, C, M, N, K, acc);
+#else
+    hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TBt>), grid, dim3(256), 0, st, A, B, C, M, N, K, acc);
+#endif
     return hipGetLastError();
 }
 
