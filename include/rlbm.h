@@ -219,8 +219,20 @@ int rlbm_batch_set_waves(rlbm_batch b, int waves);
 int rlbm_batch_get_waves(rlbm_batch b, int* waves);
 
 /*
+ * Launch mode of a batch step:
+ *   RLBM_BATCH_PERSISTENT  resident work-groups take (problem, tile) items
+ *                          from 8 XCD-local atomic work queues (default);
+ *   RLBM_BATCH_FLAT        one work-group per item, dispatched by the hardware.
+ * Both run the same tile computation, so results are identical bit for bit.
+ */
+enum { RLBM_BATCH_PERSISTENT = 0, RLBM_BATCH_FLAT = 1 };
+int rlbm_batch_set_mode(rlbm_batch b, int mode);
+int rlbm_batch_get_mode(rlbm_batch b, int* mode);
+
+/*
  * Autotuner: time `steps` graph-replayed steps for each candidate shape
- * (waves per work-group), keep the fastest and report it; the populations are
+ * (waves per work-group) in both launch modes, keep the fastest pair and
+ * report its shape (rlbm_batch_get_mode gives its mode); the populations are
  * saved before and restored after, so the state is unchanged.  Allocates a
  * temporary copy of the populations.
  */

@@ -1,6 +1,8 @@
 // batch.cpp -- the batched form of the C ABI: many independent problems of
-// uneven size advance together in one persistent launch per step, replayed
-// from a captured HIP graph, with the work-group shape chosen by an autotuner.
+// uneven size advance together in one launch per step (a persistent
+// work-queue launch or a flat launch of every (problem, tile) item), replayed
+// from a captured HIP graph, with the launch mode and work-group shape chosen
+// by an autotuner.
 #include <algorithm>
 #include <cstring>
 #include <new>
@@ -21,7 +23,9 @@ struct rlbm_batch_s {
     int total_items = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    int mode = RLBM_BATCH_PERSISTENT;
     int graph_waves = -1;        // shape the graph was captured for
+    int graph_mode = -1;         // launch mode the graph was captured for
     int desc_waves = -1;         // shape the descriptors were built for
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
@@ -46,6 +50,7 @@ void drop_graph(rlbm_batch b)
     b->exec = nullptr;
     b->graph = nullptr;
     b->graph_waves = -1;
+    b->graph_mode = -1;
 }
 
 int effective_waves(rlbm_batch b)
@@ -82,10 +87,14 @@ int upload_descs(rlbm_batch b, int waves)
     return RLBM_OK;
 }
 
-// One step: reset the 8 work counters (a small kernel, not a memset node, so
-// that the sequence can be captured in a graph) and run the persistent step.
+// One step.  Persistent mode: reset the 8 work counters (a small kernel, not
+// a memset node, so that the sequence can be captured in a graph) and run the
+// persistent step.  Flat mode: one work-group per item.
 hipError_t enqueue_step(rlbm_batch b, int waves, int parity)
 {
+    if (b->mode == RLBM_BATCH_FLAT)
+        return launch_batch_flat(b->prec, b->nmax, waves, b->total_items, b->d_desc, (int)b->ctx.size(), parity,
+                                 b->ctx[0]->d_Pc, b->max_np, b->st);
     hipError_t e = launch_reset_counters(b->d_counters, b->st);
     if (e != hipSuccess) return e;
     return launch_batch_step(b->prec, b->nmax, waves, b->grid, b->d_desc, (int)b->ctx.size(), b->d_counters,
@@ -114,6 +123,7 @@ int build_graph(rlbm_batch b, int waves)
         return bhip(b, e, "graph instantiate");
     }
     b->graph_waves = waves;
+    b->graph_mode = b->mode;
     return RLBM_OK;
 }
 
@@ -132,7 +142,7 @@ int step_impl(rlbm_batch b, int nsteps, int use_graph)
         if (rc != RLBM_OK) return rc;
         b->desc_waves = waves;
     }
-    if (use_graph && b->graph_waves != waves) {
+    if (use_graph && (b->graph_waves != waves || b->graph_mode != b->mode)) {
         const int rc = build_graph(b, waves);
         if (rc != RLBM_OK) return rc;
     }
@@ -283,21 +293,24 @@ int rlbm_batch_autotune(rlbm_batch b, const int* candidates, int ncand, int step
         else if (hipMemcpy(saved[i], b->ctx[i]->f[parity0], bytes, hipMemcpyDeviceToDevice) != hipSuccess)
             rc = bfail(b, RLBM_EDEVICE, "autotune backup copy");
     }
-    const int keep = b->waves;
-    int bw = 0;
+    const int keep = b->waves, keep_mode = b->mode;
+    int bw = 0, bm = keep_mode;
     double bms = 1e300;
-    for (int k = 0; k < ncand && rc == RLBM_OK; ++k) {
-        const int w = candidates[k];
-        if (w < 1 || w > 16) continue;
-        b->waves = w;
-        double ms = 0.0;
-        if (step_impl(b, 2, 1) != RLBM_OK) continue;   // warm-up, graph build
-        if (rlbm_batch_step_timed(b, steps, &ms) != RLBM_OK) continue;
-        if (ms < bms) {
-            bms = ms;
-            bw = w;
+    for (int k = 0; k < ncand && rc == RLBM_OK; ++k)
+        for (int mode = RLBM_BATCH_PERSISTENT; mode <= RLBM_BATCH_FLAT; ++mode) {
+            const int w = candidates[k];
+            if (w < 1 || w > 16) continue;
+            b->waves = w;
+            b->mode = mode;
+            double ms = 0.0;
+            if (step_impl(b, 2, 1) != RLBM_OK) continue;   // warm-up, graph build
+            if (rlbm_batch_step_timed(b, steps, &ms) != RLBM_OK) continue;
+            if (ms < bms) {
+                bms = ms;
+                bw = w;
+                bm = mode;
+            }
         }
-    }
     for (size_t i = 0; i < b->ctx.size(); ++i) {
         if (saved[i]) {
             size_t bytes = 0;
@@ -310,15 +323,33 @@ int rlbm_batch_autotune(rlbm_batch b, const int* candidates, int ncand, int step
     set_parity(b, parity0);
     if (rc != RLBM_OK) {
         b->waves = keep;
+        b->mode = keep_mode;
         return rc;
     }
     if (!bw) {
         b->waves = keep;
+        b->mode = keep_mode;
         return bfail(b, RLBM_EDEVICE, "no candidate shape ran");
     }
     b->waves = bw;
+    b->mode = bm;
     if (best_waves) *best_waves = bw;
     if (best_ms) *best_ms = bms;
+    return RLBM_OK;
+}
+
+int rlbm_batch_set_mode(rlbm_batch b, int mode)
+{
+    if (!b) return RLBM_EINVAL;
+    if (mode != RLBM_BATCH_PERSISTENT && mode != RLBM_BATCH_FLAT) return bfail(b, RLBM_EINVAL, "unknown launch mode");
+    b->mode = mode;
+    return RLBM_OK;
+}
+
+int rlbm_batch_get_mode(rlbm_batch b, int* mode)
+{
+    if (!b || !mode) return RLBM_EINVAL;
+    *mode = b->mode;
     return RLBM_OK;
 }
 

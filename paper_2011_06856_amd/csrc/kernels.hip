@@ -298,6 +298,27 @@ __global__ __launch_bounds__(1024) void k_batch_step(const BatchDesc* __restrict
     }
 }
 
+// Batched form, flat launch: one work-group per (problem, tile) item, no work
+// queue; the hardware dispatcher balances the items.
+template <typename TS, typename TC, int NM, int VPT>
+__global__ __launch_bounds__(1024) void k_batch_flat(const BatchDesc* __restrict__ descs, int nprob, int parity,
+                                                     const double* __restrict__ Pc)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    using CDesc = const RLBM_CONST_AS BatchDesc;
+    int p = 0;   // problem owning the item: items of a problem are contiguous
+    int step = 1;
+    while (step * 2 <= nprob) step *= 2;
+    for (; step > 0; step >>= 1)
+        if (p + step < nprob && ((CDesc*)descs)[p + step].item0 <= item) p += step;
+    CDesc& D = ((CDesc*)descs)[p];
+    const SCParams P = D.P;
+    sc_tile<TS, TC, NM, VPT>(static_cast<const TS*>(D.f[parity]), static_cast<TS*>(D.f[parity ^ 1]),
+                             static_cast<const SRec<TC>*>(P.srec), static_cast<const CRec<TC, NM>*>(P.crec), P.G, Pc,
+                             P, item - D.item0, smem);
+}
+
 __global__ void k_reset_counters(int* counters)
 {
     if (threadIdx.x < 8) counters[threadIdx.x * 16] = 0;
@@ -447,6 +468,17 @@ hipError_t launch_batch_t(int waves, int grid, const BatchDesc* descs, int nprob
     return hipGetLastError();
 }
 
+template <typename TS, typename TC, int NM, int VPT>
+hipError_t launch_batch_flat_t(int waves, int items, const BatchDesc* descs, int nprob, int parity,
+                               const double* Pc, int max_np, hipStream_t st)
+{
+    const size_t lds = batch_lds<TS, TC, NM, VPT>(waves, max_np);
+    if (lds > 160 * 1024 - 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_batch_flat<TS, TC, NM, VPT>), dim3(items), dim3(64 * waves), lds, st, descs, nprob, parity,
+                       Pc);
+    return hipGetLastError();
+}
+
 // Resident work-groups for a persistent launch: occupancy per CU times CUs.
 template <typename TS, typename TC, int NM, int VPT>
 int batch_grid_t(int waves, int max_np)
@@ -455,9 +487,12 @@ int batch_grid_t(int waves, int max_np)
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     const size_t lds = batch_lds<TS, TC, NM, VPT>(waves, max_np);
-    if (lds > 64 * 1024)
+    if (lds > 64 * 1024) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_step<TS, TC, NM, VPT>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_flat<TS, TC, NM, VPT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    }
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_batch_step<TS, TC, NM, VPT>),
                                                      64 * waves, lds) != hipSuccess)
         return 0;
@@ -503,6 +538,25 @@ hipError_t launch_batch_step(int prec, int nmax, int waves, int grid, const Batc
 #define RLBM_BATCH_CASE(TS, TC, NM)                                                                            \
     return launch_batch_t<TS, TC, NM, BVpt<TC, NM>::value>(waves, grid, descs, nprob, counters, bounds, parity, Pc, \
                                                            max_np, st)
+    if (prec == RLBM_F32) {
+        if (nmax == 3) RLBM_BATCH_CASE(float, float, 3);
+        if (nmax == 5) RLBM_BATCH_CASE(float, float, 5);
+        if (nmax == 7) RLBM_BATCH_CASE(float, float, 7);
+    } else if (prec == RLBM_F64) {
+        if (nmax == 3) RLBM_BATCH_CASE(double, double, 3);
+        if (nmax == 5) RLBM_BATCH_CASE(double, double, 5);
+        if (nmax == 7) RLBM_BATCH_CASE(double, double, 7);
+    }
+#undef RLBM_BATCH_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_flat(int prec, int nmax, int waves, int items, const BatchDesc* descs, int nprob, int parity,
+                             const double* Pc, int max_np, hipStream_t st)
+{
+    if (waves < 1 || waves > 16 || items < 1) return hipErrorInvalidValue;
+#define RLBM_BATCH_CASE(TS, TC, NM) \
+    return launch_batch_flat_t<TS, TC, NM, BVpt<TC, NM>::value>(waves, items, descs, nprob, parity, Pc, max_np, st)
     if (prec == RLBM_F32) {
         if (nmax == 3) RLBM_BATCH_CASE(float, float, 3);
         if (nmax == 5) RLBM_BATCH_CASE(float, float, 5);

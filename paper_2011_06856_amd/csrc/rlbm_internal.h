@@ -272,6 +272,8 @@ hipError_t launch_batch_step(int prec, int nmax, int waves, int grid, const Batc
                              int* counters, const int* bounds, int parity, const double* Pc, int max_np,
                              hipStream_t st);
 hipError_t launch_reset_counters(int* counters, hipStream_t st);
+hipError_t launch_batch_flat(int prec, int nmax, int waves, int items, const BatchDesc* descs, int nprob, int parity,
+                             const double* Pc, int max_np, hipStream_t st);
 
 // Push kernel (push.hip).
 void push_free(rlbm_ctx c);

@@ -53,6 +53,8 @@ SIGNATURES = [
     ("rlbm_batch_step_timed", ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     ("rlbm_batch_set_waves", ctypes.c_int, [_vp, ctypes.c_int]),
     ("rlbm_batch_get_waves", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
+    ("rlbm_batch_set_mode", ctypes.c_int, [_vp, ctypes.c_int]),
+    ("rlbm_batch_get_mode", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
     ("rlbm_batch_autotune", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int,
                                            ctypes.POINTER(ctypes.c_int), _dp]),
     ("rlbm_mlp_create", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -362,15 +364,27 @@ class Batch:
         self._check(lib().rlbm_batch_get_waves(self._h, ctypes.byref(w)))
         return w.value
 
+    MODES = {"persistent": 0, "flat": 1}
+
+    def set_mode(self, mode):
+        """Launch mode of a step: "persistent" (work queues) or "flat"."""
+        self._check(lib().rlbm_batch_set_mode(self._h, self.MODES[mode]))
+
+    def get_mode(self):
+        m = ctypes.c_int()
+        self._check(lib().rlbm_batch_get_mode(self._h, ctypes.byref(m)))
+        return {v: k for k, v in self.MODES.items()}[m.value]
+
     def autotune(self, candidates=(2, 3, 4, 6, 8), steps=6, cache=None, key=None):
-        """Pick the fastest work-group shape; with `cache` (a JSON file path)
-        and `key`, reuse a stored choice or store the new one."""
+        """Pick the fastest work-group shape and launch mode; with `cache` (a
+        JSON file path) and `key`, reuse a stored choice or store the new one."""
         import json
         if cache and key and os.path.exists(cache):
             try:
                 d = json.load(open(cache))
                 if key in d:
                     self.set_waves(d[key]["waves"])
+                    self.set_mode(d[key].get("mode", "persistent"))
                     return d[key]["waves"], d[key]["ms"]
             except (ValueError, KeyError):
                 pass
@@ -385,7 +399,7 @@ class Batch:
                     d = json.load(open(cache))
                 except ValueError:
                     d = {}
-            d[key] = {"waves": bw.value, "ms": bms.value}
+            d[key] = {"waves": bw.value, "mode": self.get_mode(), "ms": bms.value}
             json.dump(d, open(cache, "w"), indent=1)
         return bw.value, bms.value
 

@@ -45,13 +45,15 @@ def small_problems(seed=0, count=6):
     return out
 
 
-@pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_batch_problem_equals_single_run_bitwise(prec):
+@pytest.mark.parametrize("prec,mode", [("f32", "persistent"), ("f64", "persistent"), ("f32", "flat"), ("f64", "flat")])
+def test_batch_problem_equals_single_run_bitwise(prec, mode):
     rl = _rlbm()
     probs = small_problems(1)
     b = rl.Batch(probs, precision=prec)
+    b.set_mode(mode)
+    assert b.get_mode() == mode
     waves = b.get_waves()
-    say("batch %s waves=%d problems=%d" % (prec, waves, len(b)))
+    say("batch %s %s waves=%d problems=%d" % (prec, mode, waves, len(b)))
     b.step(7)          # odd: graph pairs plus one eager step
     for i, p in enumerate(probs):
         s = rl.Solver(p["Np"], p["K"], p["N"]).init_fields(p["nx"], p["ny"], *p["fields"], tau=p["tau"],
@@ -106,7 +108,8 @@ def test_autotune_keeps_state_and_picks_a_candidate(tmp_path):
     before = [b.problem(i).get_populations().copy() for i in range(len(b))]
     cache = str(tmp_path / "tune.json")
     w, ms = b.autotune(candidates=(1, 2, 4), steps=4, cache=cache, key="test")
-    assert w in (1, 2, 4) and ms > 0
+    assert w in (1, 2, 4) and ms > 0 and b.get_mode() in ("persistent", "flat")
+    mode = b.get_mode()
     for i in range(len(b)):
         assert np.array_equal(b.problem(i).get_populations(), before[i])
     assert b.autotune(candidates=(1, 2, 4), cache=cache, key="test")[0] == w   # from the cache
@@ -114,6 +117,7 @@ def test_autotune_keeps_state_and_picks_a_candidate(tmp_path):
     ref = rl.Batch(probs)
     ref.step(3)
     ref.set_waves(w)
+    ref.set_mode(mode)
     b.step(2)
     ref.step(2)
     for i in range(len(b)):
