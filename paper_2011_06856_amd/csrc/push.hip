@@ -13,11 +13,14 @@
 //   f_v at y, y - sx, y - sy, y - sx - sy (Eq. interpolation), so
 //     M_k(y) = sum_v P_k(v) f*_v(y) = sum over sources s and corners c of
 //              sum_{v with corner c at s} w_c(v) P_k(v) f_v(s).
-//   While a wave writes f_v(s) it accumulates these per-source partial sums
-//   (a centre slot and three displaced corners per quadrant of (sx, sy):
-//   13 slots x 8 moments per site) and stores them; the next step gathers
-//   its moments from the 13 slots of the 3x3 neighbourhood, with the same
-//   periodic or clamped index rules as the stream.
+//   While a wave writes f_v(s) it accumulates these per-source partial sums.
+//   The x-displaced parts (targets s + sx) are moved to their target column
+//   inside the wave by a cross-lane shuffle, so each site stores three row
+//   slots (its contributions to rows y - 1, y, y + 1 at its own column) x 8
+//   moments; the tile's first and last columns also store their x-displaced
+//   parts in a small halo array (the parts that leave the tile, and the
+//   images a clamped boundary needs).  The next step gathers its moments
+//   from the three rows, with the stream's periodic or clamped index rules.
 //
 // A wave then owns 64 sites of one row and runs through all velocities once:
 // stream, equilibrium, relaxation, store and partial sums, with no
@@ -36,11 +39,6 @@
 #define PUSH_CONST_AS __attribute__((address_space(4)))
 #else
 #define PUSH_CONST_AS
-#endif
-
-// Work-group barrier every RLBM_PUSH_SYNC load batches (0: none).
-#ifndef RLBM_PUSH_SYNC
-#define RLBM_PUSH_SYNC 0
 #endif
 
 namespace {
@@ -90,7 +88,6 @@ struct PushParams {
     int* flag;
 };
 
-constexpr int NSLOT = 13;   // centre + 3 displaced corners x 4 quadrants
 constexpr int NMOM = 8;     // N^0 N^x N^y T^00 T^0x T^0y T^xx T^xy
 
 // Quadrant q: upwind signs sx = +1 for q in {0, 1}, sy = +1 for q in {0, 3}.
@@ -114,12 +111,28 @@ __device__ __forceinline__ int xcd_remap_p(int b, int nb)
     return k * q + min(k, r) + j;
 }
 
+// Partial sums of a buffer (element type T):
+//   R[d][k][S]   row slots: the contributions of the sources at (x, y) to the
+//                moments k of the sites in row y + dy at column x, d = 0, 1, 2
+//                for dy = 0, +1, -1 (the x-displaced parts already moved to
+//                their target column inside the wave);
+//   H[edge][dir][d][k][ny][ntx]   the x-displaced parts of the first (edge 0)
+//                and last (edge 1) column of each tile, for sx = +1 (dir 0)
+//                and sx = -1 (dir 1): the parts that leave the tile, and the
+//                images a clamped boundary needs.
+__host__ __device__ inline long long halo_off(long long S, int edge, int dir, int d, int k, int row, int tc, int ny,
+                                              int ntx)
+{
+    return 3LL * NMOM * S + ((((long long)(edge * 2 + dir) * 3 + d) * NMOM + k) * ny + row) * ntx + tc;
+}
+
 // One wave-tile: 64 sites of row ty starting at column 64 tx.  INIT computes
 // only the partial sums of the current populations (no stream, no
-// collision, no population store).
+// collision, no population store).  lh: this wave's LDS, the 96-entry halo
+// accumulator [edge][dir][d][k] followed by the row slots [d][k][64].
 template <typename T, int NM, int LB, bool INIT>
 __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ pin,
-                                          T* __restrict__ pout, const PushParams& P, int tile, T* __restrict__ lacc,
+                                          T* __restrict__ pout, const PushParams& P, int tile, T* __restrict__ lh,
                                           bool live)
 {
     constexpr int NT = 2 * NM + 1;
@@ -139,6 +152,7 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
     const int ty = tile / ntx;
     const int tx = tile - ty * ntx;
     const int x = tx * 64 + lane;
+    const int last = min(63, P.nx - 1 - tx * 64);   // last column of the tile, as a lane
     const bool active = x < P.nx && live;
     const int xc = x < P.nx ? x : P.nx - 1;
     const bool interior = tx > 0 && (tx + 1) * 64 < P.nx && live;
@@ -146,27 +160,32 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
     const int xm = wrapi(xc - 1, P.nx, P.bcx), xp = wrapi(xc + 1, P.nx, P.bcx);
     const int ym = wrapi(ty - 1, P.ny, P.bcy), yp = wrapi(ty + 1, P.ny, P.bcy);
     const long long site = (long long)ty * P.nx + xc;
+    const int rows[3] = {ty, ym, yp};   // source row of the slot d = 0 (dy 0), 1 (dy +1), 2 (dy -1)
 
     // 1. moments of the streamed populations, gathered from the partial sums
-    //    pushed by the previous step (FP64 sum of the 13 contributions)
+    //    pushed by the previous step: the three row slots at this column, and
+    //    for the first / last column of the tile the halo parts of the
+    //    upwind column outside it (FP64 sums)
     T a0 = T(0), ax = T(0), ay = T(0);
     double fn_ = 0, fT = 0, fU0 = 0, fUx = 0, fUy = 0;
     int ok = 0;
     if (!INIT) {
-        // one moment at a time (13 loads in flight) so that the gather does
-        // not set the kernel's register peak
+        const int cl = wrapi(tx * 64 - 1, P.nx, P.bcx);            // column left of the tile
+        const int cr = wrapi(tx * 64 + last + 1, P.nx, P.bcx);     // column right of the tile
+        const int el = (cl & 63) == 0 ? 0 : 1, er = (cr & 63) == 0 ? 0 : 1;
         double mom[9];
 #pragma unroll 1
         for (int k = 0; k < NMOM; ++k) {
-            double s = (double)pin[(long long)k * S + site];
+            double s = 0.0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int cx = qsx(q) > 0 ? xm : xp;     // column x - sx
-                const long long ry = (long long)(qsy(q) > 0 ? ym : yp) * P.nx;   // row y - sy
-                const T* b = pin + (long long)((1 + 3 * q) * NMOM + k) * S;
-                s += (double)b[(long long)ty * P.nx + cx];
-                s += (double)b[NMOM * S + ry + xc];
-                s += (double)b[2 * NMOM * S + ry + cx];
+            for (int d = 0; d < 3; ++d) s += (double)pin[(long long)(d * NMOM + k) * S + (long long)rows[d] * P.nx + xc];
+            if (lane == 0) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) s += (double)pin[halo_off(S, el, 0, d, k, rows[d], cl >> 6, P.ny, ntx)];
+            }
+            if (lane == last) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) s += (double)pin[halo_off(S, er, 1, d, k, rows[d], cr >> 6, P.ny, ntx)];
             }
             mom[k] = s;
         }
@@ -192,40 +211,49 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
     auto ld = [](const char* base, unsigned off) __attribute__((always_inline)) -> T {
         return *reinterpret_cast<const T*>(base + off);
     };
+    const T act = active ? T(1) : T(0);   // columns past the grid contribute nothing
+    // value of lane (lane - sx), zero where that lane is outside the wave
+    auto from_upwind = [&](T v, int sx) __attribute__((always_inline)) -> T {
+        const int src = lane - sx;
+        const T r = __shfl(v, src & 63, 64);
+        return (src < 0 || src > 63) ? T(0) : r;
+    };
 
-    // The 32 weighted moment sums of the current quadrant (centre slot and
-    // three displaced corners) are touched once per segment: they live in
-    // this wave's LDS (lane-contiguous, [slot][k][64]), not in registers.
-    // lacc[c][k]: c = 0 centre (all quadrants), 1..3 the quadrant's corners.
-    auto L = [&](int c, int k) __attribute__((always_inline)) -> T& { return lacc[(c * NMOM + k) * 64 + lane]; };
+    for (int j = lane; j < 96; j += 64) lh[j] = T(0);
+    // row slots d = 0, 1, 2 (dy 0, +1, -1), touched once per segment: in
+    // this wave's LDS after the halo accumulator, lane-contiguous
+    T* const lrow = lh + 96;
+    auto R = [&](int d, int k) __attribute__((always_inline)) -> T& { return lrow[(d * NMOM + k) * 64 + lane]; };
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int k = 0; k < NMOM; ++k) L(c, k) = T(0);
+        for (int k = 0; k < NMOM; ++k) R(d, k) = T(0);
     const T dt = (T)P.dt;
 
-    // 2. the velocities, quadrant by quadrant and shell by shell; interior
-    //    tiles (FAST) reach the x neighbour by a scalar shift of the plane
-    //    offset and store without a lane mask
+    // 2. the velocities, shell by shell and, inside a shell, quadrant by
+    //    quadrant; interior tiles (FAST) reach the x neighbour by a scalar
+    //    shift of the plane offset and store without a lane mask
     auto run = [&](auto fast) __attribute__((always_inline)) {
         constexpr bool FAST = decltype(fast)::value;
-        for (int q = 0; q < 4; ++q) {
-            const T al = dt * (T)qsx(q), be = dt * (T)qsy(q), ga = al * be;
-            for (int i = 0; i < P.Np; ++i) {
+        for (int i = 0; i < P.Np; ++i) {
+            T cc[NT];
+            if (!INIT) {
+                shell_coeffs<NM>(Gtab + (size_t)i * GS, Pc, fn_, fT, fU0, fUx, fUy,
+                                 [&](int mm, double cm, double sm) __attribute__((always_inline)) {
+                                     if (!ok) cm = sm = 0.0;
+                                     if (mm == 0) {
+                                         cc[0] = (T)cm;
+                                     } else {
+                                         cc[2 * mm - 1] = (T)cm;
+                                         cc[2 * mm] = (T)sm;
+                                     }
+                                 });
+            }
+#pragma unroll 1
+            for (int q = 0; q < 4; ++q) {
+                const int sx = qsx(q), sy = qsy(q);
+                const int dY = sy > 0 ? 1 : 2;   // row slot of the y-displaced parts
                 CSeg& G = seg[q * P.Np + i];
-                T cc[NT];
-                if (!INIT) {
-                    shell_coeffs<NM>(Gtab + (size_t)i * GS, Pc, fn_, fT, fU0, fUx, fUy,
-                                     [&](int mm, double cm, double sm) __attribute__((always_inline)) {
-                                         if (!ok) cm = sm = 0.0;
-                                         if (mm == 0) {
-                                             cc[0] = (T)cm;
-                                         } else {
-                                             cc[2 * mm - 1] = (T)cm;
-                                             cc[2 * mm] = (T)sm;
-                                         }
-                                     });
-                }
                 T Sm[9];   // sum f, f c, f s, f c^2, f c s, f c^3, f c^2 s, f c^3 s, f c^2 s^2
 #pragma unroll
                 for (int j = 0; j < 9; ++j) Sm[j] = T(0);
@@ -235,17 +263,17 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
                     T raw[LB][4];
 #pragma unroll
                     for (int b = 0; b < LB; ++b) {
-                        CAddr& R = adr[v0 + kb * LB + b];
-                        const char* p0 = inb + R.roff;
+                        CAddr& A = adr[v0 + kb * LB + b];
+                        const char* p0 = inb + A.roff;
                         if (INIT) {
                             raw[b][0] = ld(p0, ocb);
                         } else {
-                            const char* p1 = p0 + (R.sy > 0 ? dmb : dpb);
+                            const char* p1 = p0 + (A.sy > 0 ? dmb : dpb);
                             if (FAST) {
-                                raw[b][0] = ld(p0, ocb); raw[b][1] = ld(p0 + R.dx, ocb);
-                                raw[b][2] = ld(p1, ocb); raw[b][3] = ld(p1 + R.dx, ocb);
+                                raw[b][0] = ld(p0, ocb); raw[b][1] = ld(p0 + A.dx, ocb);
+                                raw[b][2] = ld(p1, ocb); raw[b][3] = ld(p1 + A.dx, ocb);
                             } else {
-                                const unsigned osb = R.dx < 0 ? omb : opb;
+                                const unsigned osb = A.dx < 0 ? omb : opb;
                                 raw[b][0] = ld(p0, ocb); raw[b][1] = ld(p0, osb);
                                 raw[b][2] = ld(p1, ocb); raw[b][3] = ld(p1, osb);
                             }
@@ -253,42 +281,44 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
                     }
 #pragma unroll
                     for (int b = 0; b < LB; ++b) {
-                        CRec& R = rec[v0 + kb * LB + b];
+                        CRec& Rr = rec[v0 + kb * LB + b];
                         T fnew;
                         if (INIT) {
-                            // null records (zero equilibrium row) contribute nothing;
-                            // real ones exactly their value, as in the step
-                            fnew = R.H[0] != T(0) ? raw[b][0] : T(0);
+                            // padding records (zero equilibrium row) contribute
+                            // nothing; real ones exactly their value, as in the step
+                            fnew = Rr.H[0] != T(0) ? raw[b][0] : T(0);
                         } else {
-                            const T f = R.w[0] * raw[b][0] + R.w[1] * raw[b][1] + R.w[2] * raw[b][2] +
-                                        R.w[3] * raw[b][3];
-                            T feq = cc[0] * R.H[0];
+                            const T f = Rr.w[0] * raw[b][0] + Rr.w[1] * raw[b][1] + Rr.w[2] * raw[b][2] +
+                                        Rr.w[3] * raw[b][3];
+                            T feq = cc[0] * Rr.H[0];
 #pragma unroll
-                            for (int t = 1; t < NT; ++t) feq += cc[t] * R.H[t];
-                            const T om = a0 - ax * R.cth - ay * R.sth;
+                            for (int t = 1; t < NT; ++t) feq += cc[t] * Rr.H[t];
+                            const T om = a0 - ax * Rr.cth - ay * Rr.sth;
                             fnew = f + om * (feq - f);
                             // non-temporal: the next read of this plane is a step away
-                            T* dst = reinterpret_cast<T*>(outb + R.woff + ocb);
+                            T* dst = reinterpret_cast<T*>(outb + Rr.woff + ocb);
 #ifndef RLBM_TEMPORAL_STORE
                             if (FAST || active) __builtin_nontemporal_store(fnew, dst);
 #else
                             if (FAST || active) *dst = fnew;
 #endif
                         }
+                        // explicit FMAs: the step and the rebuild (INIT) must
+                        // produce the same partial sums bit for bit
                         Sm[0] += fnew;
 #pragma unroll
-                        for (int j = 0; j < 8; ++j) Sm[1 + j] += fnew * R.mono[j];
+                        for (int j = 0; j < 8; ++j) Sm[1 + j] = fma(fnew, (T)Rr.mono[j], Sm[1 + j]);
                     }
-#if RLBM_PUSH_SYNC
-                    // keep the work-group's 4 row-waves within a few batches of
-                    // each other, so that the rows they share are fetched once
-                    if (!INIT && (kb % RLBM_PUSH_SYNC) == RLBM_PUSH_SYNC - 1) __syncthreads();
-#endif
                 }
                 // fold the monomial sums into the weighted moment sums of the
                 // segment's four corners: with T_e = sum f e, the corner sums
-                // of e are C0 = T_e - al T_ce - be T_se + ga T_cse, C1 = al
-                // T_ce - ga T_cse, C2 = be T_se - ga T_cse, C3 = ga T_cse
+                // of e are C0 = T_e - al T_ce - be T_se + ga T_cse (target
+                // (x, y)), C1 = al T_ce - ga T_cse (x + sx, y), C2 = be T_se -
+                // ga T_cse (x, y + sy), C3 = ga T_cse (x + sx, y + sy).  No
+                // contraction here, so that both instantiations round alike.
+                {
+#pragma clang fp contract(off)
+                const T al = dt * (T)sx, be = dt * (T)sy, ga = al * be;
                 const T S1 = Sm[0], Sc = Sm[1], Ss = Sm[2], Scc = Sm[3], Scs = Sm[4], Sccc = Sm[5], Sccs = Sm[6],
                         Scccs = Sm[7], Sccss = Sm[8];
                 const T Sss = S1 - Scc, Scss = Sc - Sccc;
@@ -301,36 +331,54 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
                 const T p = (T)G.p, p2 = (T)(G.p * G.p);
                 // moment k: angular factor e(k), radial factor p or p^2
                 constexpr int EK[NMOM] = {0, 1, 2, 0, 1, 2, 3, 4};
+                const int dir = sx > 0 ? 0 : 1;
 #pragma unroll
                 for (int k = 0; k < NMOM; ++k) {
                     const T* t4 = Te[EK[k]];
                     const T r = k < 3 ? p : p2;
-                    const T c3 = ga * t4[3];
-                    const T c1 = al * t4[1] - c3;
-                    const T c2 = be * t4[2] - c3;
-                    const T c0 = t4[0] - c1 - c2 - c3;
-                    L(0, k) += r * c0;
-                    L(1, k) += r * c1;
-                    L(2, k) += r * c2;
-                    L(3, k) += r * c3;
+                    const T c3 = act * r * (ga * t4[3]);
+                    const T c1 = act * r * (al * t4[1]) - c3;
+                    const T c2 = act * r * (be * t4[2]) - c3;
+                    const T c0 = act * r * t4[0] - c1 - c2 - c3;
+                    // x-displaced parts move to their target column inside the
+                    // wave; the tile's edge columns also keep them for the halo
+                    R(0, k) += c0 + from_upwind(c1, sx);
+                    R(dY, k) += c2 + from_upwind(c3, sx);
+                    if (lane == 0) {
+                        lh[((0 * 2 + dir) * 3 + 0) * NMOM + k] += c1;
+                        lh[((0 * 2 + dir) * 3 + dY) * NMOM + k] += c3;
+                    }
+                    if (lane == last) {
+                        lh[((1 * 2 + dir) * 3 + 0) * NMOM + k] += c1;
+                        lh[((1 * 2 + dir) * 3 + dY) * NMOM + k] += c3;
+                    }
+                }
                 }
             }
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int k = 0; k < NMOM; ++k) {
-                    if (FAST || active) pout[(long long)((1 + 3 * q + c) * NMOM + k) * S + site] = L(1 + c, k);
-                    L(1 + c, k) = T(0);
-                }
         }
     };
     if (interior)
         run(std::true_type{});
     else
         run(std::false_type{});
+
+    // 3. partial sums for the next step: row slots of every column, halo
+    //    parts of the tile's first and last columns
     if (interior || active) {
 #pragma unroll
-        for (int k = 0; k < NMOM; ++k) pout[(long long)k * S + site] = L(0, k);
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int k = 0; k < NMOM; ++k) pout[(long long)(d * NMOM + k) * S + site] = R(d, k);
+    }
+    if (live && (lane == 0 || lane == last)) {
+#pragma unroll 1
+        for (int ed = 0; ed < 2; ++ed) {
+            if ((ed == 0 && lane != 0) || (ed == 1 && lane != last)) continue;
+            for (int dir = 0; dir < 2; ++dir)
+                for (int d = 0; d < 3; ++d)
+                    for (int k = 0; k < NMOM; ++k)
+                        pout[halo_off(S, ed, dir, d, k, ty, tx, P.ny, ntx)] = lh[((ed * 2 + dir) * 3 + d) * NMOM + k];
+        }
     }
 }
 
@@ -355,18 +403,11 @@ __global__ __launch_bounds__(256, RLBM_PUSH_WPE) void k_push_step(const T* __res
     const int b = xcd_remap_p(blockIdx.x, gridDim.x);
     const int band = b / ntx;
     const int ty = band * 4 + wv;
-#if RLBM_PUSH_SYNC
-    // rows past the grid (last band) run the same loop on the last row with
-    // every store off, so that all waves meet the same barriers
-    const bool live = ty < P.ny;
-    const int tile = (live ? ty : P.ny - 1) * ntx + (b - band * ntx);
-#else
-    if (ty >= P.ny) return;   // whole waves; no barrier follows
+    if (ty >= P.ny) return;   // whole waves; the kernel has no barrier
     const bool live = true;
     const int tile = ty * ntx + (b - band * ntx);
-#endif
-    T* lacc = reinterpret_cast<T*>(psmem) + (size_t)wv * 4 * NMOM * 64;
-    push_tile<T, NM, LB, INIT>(fin, fout, pin, pout, P, tile, lacc, live);
+    T* lh = reinterpret_cast<T*>(psmem) + (size_t)wv * (96 + 3 * NMOM * 64);
+    push_tile<T, NM, LB, INIT>(fin, fout, pin, pout, P, tile, lh, live);
 }
 
 // Load batch per precision: FP64 holds half as many values per register.
@@ -381,7 +422,7 @@ hipError_t launch_push_t(bool init, const void* fin, void* fout, const void* pin
 {
     constexpr int LB = PushLB<T>::value;
     const unsigned blocks = (unsigned)(((P.nx + 63) / 64) * ((P.ny + 3) / 4));
-    const size_t lds = (size_t)4 * 4 * NMOM * 64 * sizeof(T);   // 4 waves x 32 sums x 64 lanes
+    const size_t lds = (size_t)4 * (96 + 3 * NMOM * 64) * sizeof(T);   // 4 waves x (halo + row slots)
     if (init)
         hipLaunchKernelGGL((k_push_step<T, NM, LB, true>), dim3(blocks), dim3(256), lds, st, (const T*)fin, (T*)fout,
                            (const T*)pin, (T*)pout, P);
@@ -467,7 +508,8 @@ int upload_push_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, int precisi
         err = hipGetErrorString(e);
         return RLBM_EDEVICE;
     }
-    const size_t pbytes = (size_t)NSLOT * NMOM * S * sizeof(T);
+    const int ntx = (c->nx + 63) / 64;
+    const size_t pbytes = ((size_t)3 * NMOM * S + (size_t)2 * 2 * 3 * NMOM * c->ny * ntx) * sizeof(T);
     for (int b = 0; b < 2; ++b)
         if ((e = hipMalloc(&c->pp[b], pbytes)) != hipSuccess) return RLBM_ENOMEM;
     (void)precision;
