@@ -159,7 +159,8 @@ int rlbm_set_waves(rlbm_ctx ctx, int waves);
  *                     two library-owned device buffers allocated on first
  *                     use; recomputed after any external change of the
  *                     populations);
- *   RLBM_KERNEL_AUTO  (default) PUSH from 768 velocities on, else TILE.
+ *   RLBM_KERNEL_AUTO  (default) PUSH from 320 velocities on, else TILE
+ *                     (measured crossover between 256 and 384).
  * The results agree to rounding.  rlbm_get_kernel returns the kernel that
  * rlbm_step uses.  RLBM_EINVAL for an unknown kind.
  */

@@ -205,7 +205,7 @@ struct SCParams {
 
 // Velocity count from which RLBM_KERNEL_AUTO selects the push kernel.
 #ifndef RLBM_PUSH_MIN_NVEL
-#define RLBM_PUSH_MIN_NVEL 768
+#define RLBM_PUSH_MIN_NVEL 320
 #endif
 
 #ifndef RLBM_BAND_DEFAULT

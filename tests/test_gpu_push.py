@@ -153,8 +153,9 @@ def test_partial_sums_follow_external_changes():
 
 
 def test_push_fp32_matches_oracle_after_1000_steps():
-    """FP32 populations, Np=4 x K=192 (768 velocities, the automatic switch
-    point), 1000 steps, Kn = 0.01 and 1, on a 48 x 40 periodic grid."""
+    """FP32 populations, Np=4 x K=192 (768 velocities, where the automatic
+    choice is the push kernel), 1000 steps, Kn = 0.01 and 1, on a 48 x 40
+    periodic grid."""
     rl = _rlbm()
     nx, ny = 48, 40
     for Kn in (0.01, 1.0):
