@@ -12,6 +12,12 @@
 
 struct rlbm_batch_s {
     std::vector<rlbm_ctx> ctx;   // one context per problem (own buffers and tables)
+    // problems stepped by the tile kernel (persistent or flat launch) and by
+    // the push kernel (one flat launch of 4-row work-groups), by the same
+    // automatic choice as a single problem
+    std::vector<int> tile_ix, push_ix;
+    void* d_pdesc = nullptr;     // push descriptors
+    int push_wgs = 0;
     std::string err;
     int prec = RLBM_F32, nmax = 3, max_np = 1, waves = 0, grid = 0;
     hipStream_t st = nullptr;
@@ -56,18 +62,19 @@ void drop_graph(rlbm_batch b)
 int effective_waves(rlbm_batch b)
 {
     if (b->waves) return b->waves;
-    int nv = 0;   // the largest velocity set decides the default shape
-    for (rlbm_ctx c : b->ctx) nv = std::max(nv, c->q.nvel);
+    int nv = 0;   // the largest velocity set of the tile-kernel problems decides the default shape
+    for (int i : b->tile_ix) nv = std::max(nv, b->ctx[i]->q.nvel);
+    if (!nv) nv = 64;
     return default_waves(b->prec, b->nmax, nv);
 }
 
 // Upload the descriptors for a work-group shape (chunk sizes depend on it).
 int upload_descs(rlbm_batch b, int waves)
 {
-    std::vector<BatchDesc> d(b->ctx.size());
+    std::vector<BatchDesc> d(b->tile_ix.size());
     int item = 0;
-    for (size_t i = 0; i < b->ctx.size(); ++i) {
-        rlbm_ctx c = b->ctx[i];
+    for (size_t i = 0; i < b->tile_ix.size(); ++i) {
+        rlbm_ctx c = b->ctx[b->tile_ix[i]];
         d[i].f[0] = c->f[0];
         d[i].f[1] = c->f[1];
         d[i].P = make_params(c, waves);
@@ -76,6 +83,10 @@ int upload_descs(rlbm_batch b, int waves)
         item += d[i].tiles;
     }
     b->total_items = item;
+    if (d.empty()) {
+        b->grid = 0;
+        return RLBM_OK;
+    }
     std::vector<int> bounds(9);
     for (int k = 0; k <= 8; ++k) bounds[k] = (int)((long long)item * k / 8);
     hipError_t e = hipMemcpy(b->d_desc, d.data(), d.size() * sizeof(BatchDesc), hipMemcpyHostToDevice);
@@ -90,15 +101,45 @@ int upload_descs(rlbm_batch b, int waves)
 // One step.  Persistent mode: reset the 8 work counters (a small kernel, not
 // a memset node, so that the sequence can be captured in a graph) and run the
 // persistent step.  Flat mode: one work-group per item.
+// Then the push-kernel problems in one flat launch.
 hipError_t enqueue_step(rlbm_batch b, int waves, int parity)
 {
-    if (b->mode == RLBM_BATCH_FLAT)
-        return launch_batch_flat(b->prec, b->nmax, waves, b->total_items, b->d_desc, (int)b->ctx.size(), parity,
-                                 b->ctx[0]->d_Pc, b->max_np, b->st);
-    hipError_t e = launch_reset_counters(b->d_counters, b->st);
-    if (e != hipSuccess) return e;
-    return launch_batch_step(b->prec, b->nmax, waves, b->grid, b->d_desc, (int)b->ctx.size(), b->d_counters,
-                             b->d_bounds, parity, b->ctx[0]->d_Pc, b->max_np, b->st);
+    hipError_t e = hipSuccess;
+    const int nt = (int)b->tile_ix.size();
+    if (nt > 0) {
+        if (b->mode == RLBM_BATCH_FLAT) {
+            e = launch_batch_flat(b->prec, b->nmax, waves, b->total_items, b->d_desc, nt, parity, b->ctx[0]->d_Pc,
+                                  b->max_np, b->st);
+        } else {
+            e = launch_reset_counters(b->d_counters, b->st);
+            if (e == hipSuccess)
+                e = launch_batch_step(b->prec, b->nmax, waves, b->grid, b->d_desc, nt, b->d_counters, b->d_bounds,
+                                      parity, b->ctx[0]->d_Pc, b->max_np, b->st);
+        }
+    }
+    if (e == hipSuccess && !b->push_ix.empty())
+        e = launch_push_batch(b->prec, b->nmax, b->d_pdesc, (int)b->push_ix.size(), b->push_wgs, parity, b->st);
+    return e;
+}
+
+// Push-kernel problems: tables, partial-sum buffers and the partial sums of
+// the current populations (outside any graph capture), then descriptors.
+int prepare_push(rlbm_batch b)
+{
+    if (b->push_ix.empty()) return RLBM_OK;
+    std::vector<rlbm_ctx> cs;
+    for (int i : b->push_ix) {
+        rlbm_ctx c = b->ctx[i];
+        std::string err;
+        const int rc = push_prepare(c, err);
+        if (rc != RLBM_OK) return bfail(b, rc, "push kernel setup: " + err);
+        cs.push_back(c);
+    }
+    if (!b->d_pdesc) {
+        const int rc = push_batch_descs(cs, &b->d_pdesc, &b->push_wgs);
+        if (rc != RLBM_OK) return bfail(b, rc, "push descriptors");
+    }
+    return RLBM_OK;
 }
 
 // Capture two steps (parity 0 then 1) into a graph for the current shape.
@@ -131,10 +172,15 @@ void set_parity(rlbm_batch b, int parity)
 {
     b->parity = parity;
     for (rlbm_ctx c : b->ctx) c->cur = parity;
+    for (int i : b->push_ix) b->ctx[i]->pcur = parity;   // partial sums follow the populations
 }
 
 int step_impl(rlbm_batch b, int nsteps, int use_graph)
 {
+    if (nsteps > 0) {
+        const int rc = prepare_push(b);
+        if (rc != RLBM_OK) return rc;
+    }
     const int waves = effective_waves(b);
     if (b->desc_waves != waves) {
         drop_graph(b);
@@ -208,6 +254,8 @@ int rlbm_batch_create(rlbm_batch* out, const rlbm_problem* probs, int count, int
         b->max_np = std::max(b->max_np, c->q.Np);
     }
     b->nmax = nmax;
+    for (int i = 0; i < count; ++i)
+        (resolve_kernel(b->ctx[i]) == RLBM_KERNEL_PUSH ? b->push_ix : b->tile_ix).push_back(i);
     hipError_t e = hipMalloc(&b->d_desc, sizeof(BatchDesc) * count);
     if (e == hipSuccess) e = hipMalloc(&b->d_counters, 8 * 16 * sizeof(int));
     if (e == hipSuccess) e = hipMalloc(&b->d_bounds, 16 * sizeof(int));
@@ -321,6 +369,7 @@ int rlbm_batch_autotune(rlbm_batch b, const int* candidates, int ncand, int step
         }
     }
     set_parity(b, parity0);
+    for (int i : b->push_ix) b->ctx[i]->pvalid = 0;   // populations restored: rebuild their partial sums
     if (rc != RLBM_OK) {
         b->waves = keep;
         b->mode = keep_mode;
@@ -377,6 +426,7 @@ int rlbm_batch_destroy(rlbm_batch b)
     drop_graph(b);
     for (rlbm_ctx c : b->ctx) rlbm_destroy(c);
     if (b->d_desc) (void)hipFree(b->d_desc);
+    if (b->d_pdesc) (void)hipFree(b->d_pdesc);
     if (b->d_counters) (void)hipFree(b->d_counters);
     if (b->d_bounds) (void)hipFree(b->d_bounds);
     if (b->ev0) (void)hipEventDestroy(b->ev0);

@@ -410,6 +410,43 @@ __global__ __launch_bounds__(256, RLBM_PUSH_WPE) void k_push_step(const T* __res
     push_tile<T, NM, LB, INIT>(fin, fout, pin, pout, P, tile, lh, live);
 }
 
+// Batched form: the push-kernel problems of a batch advance together in one
+// flat launch of 4-row work-groups; work-group g belongs to the problem
+// whose range [wg0, wg0 + wgs) holds it.
+struct PushDesc {
+    void* f[2];
+    void* pp[2];
+    PushParams P;
+    int wg0, wgs;
+};
+
+template <typename T, int NM, int LB>
+__global__ __launch_bounds__(256, RLBM_PUSH_WPE) void k_push_batch(const PushDesc* __restrict__ descs, int nprob,
+                                                                    int parity)
+{
+    extern __shared__ __align__(16) unsigned char psmem[];
+    using CDesc = const PUSH_CONST_AS PushDesc;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int g = xcd_remap_p(blockIdx.x, gridDim.x);
+    int p = 0;
+    int step = 1;
+    while (step * 2 <= nprob) step *= 2;
+    for (; step > 0; step >>= 1)
+        if (p + step < nprob && ((CDesc*)descs)[p + step].wg0 <= g) p += step;
+    CDesc& D = ((CDesc*)descs)[p];
+    const PushParams P = D.P;
+    const int ntx = (P.nx + 63) >> 6;
+    const int b = g - D.wg0;
+    const int band = b / ntx;
+    const int ty = band * 4 + wv;
+    if (ty >= P.ny) return;   // whole waves; the kernel has no barrier
+    const int tile = ty * ntx + (b - band * ntx);
+    T* lh = reinterpret_cast<T*>(psmem) + (size_t)wv * (96 + 3 * NMOM * 64);
+    push_tile<T, NM, LB, false>(static_cast<const T*>(D.f[parity]), static_cast<T*>(D.f[parity ^ 1]),
+                                static_cast<const T*>(D.pp[parity]), static_cast<T*>(D.pp[parity ^ 1]), P, tile, lh,
+                                true);
+}
+
 // Load batch per precision: FP64 holds half as many values per register.
 template <typename T>
 struct PushLB {
@@ -429,6 +466,16 @@ hipError_t launch_push_t(bool init, const void* fin, void* fout, const void* pin
     else
         hipLaunchKernelGGL((k_push_step<T, NM, LB, false>), dim3(blocks), dim3(256), lds, st, (const T*)fin, (T*)fout,
                            (const T*)pin, (T*)pout, P);
+    return hipGetLastError();
+}
+
+template <typename T, int NM>
+hipError_t launch_push_batch_t(const void* descs, int nprob, int wgs, int parity, hipStream_t st)
+{
+    constexpr int LB = PushLB<T>::value;
+    const size_t lds = (size_t)4 * (96 + 3 * NMOM * 64) * sizeof(T);
+    hipLaunchKernelGGL((k_push_batch<T, NM, LB>), dim3((unsigned)wgs), dim3(256), lds, st,
+                       static_cast<const PushDesc*>(descs), nprob, parity);
     return hipGetLastError();
 }
 
@@ -558,7 +605,8 @@ int push_setup(rlbm_ctx c, std::string& err)
 // One launch of the push kernel: init = 1 recomputes the partial sums of
 // the current populations into pp[pcur]; init = 0 advances one step
 // (f[cur] -> f[cur^1], pp[pcur] -> pp[pcur^1]).
-hipError_t launch_push(rlbm_ctx c, bool init)
+namespace {
+PushParams make_push_params(rlbm_ctx c)
 {
     PushParams P;
     P.paddr = static_cast<const PAddr*>(c->d_paddr);
@@ -572,6 +620,13 @@ hipError_t launch_push(rlbm_ctx c, bool init)
     P.rate = c->rate;
     P.dt = c->dt;
     P.flag = c->d_flag;
+    return P;
+}
+}  // namespace
+
+hipError_t launch_push(rlbm_ctx c, bool init)
+{
+    const PushParams P = make_push_params(c);
     const void* fin = c->f[c->cur];
     void* fout = c->f[c->cur ^ 1];
     const void* pin = c->pp[c->pcur];
@@ -585,4 +640,72 @@ hipError_t launch_push(rlbm_ctx c, bool init)
     if (nm == 3) return launch_push_t<double, 3>(init, fin, fout, pin, pout, P, c->st);
     if (nm == 5) return launch_push_t<double, 5>(init, fin, fout, pin, pout, P, c->st);
     return launch_push_t<double, 7>(init, fin, fout, pin, pout, P, c->st);
+}
+
+// Batched form.  push_prepare: tables and buffers of a push-kernel problem,
+// and its partial sums for the current populations (pcur = cur), issued on
+// the context's stream.  push_batch_wgs: its work-groups per step.
+// push_batch_descs: the device descriptors of a list of problems (device
+// array, nprob entries, allocated here; free with hipFree).
+int push_prepare(rlbm_ctx c, std::string& err)
+{
+    if (!c->d_prec) {
+        const int rc = push_setup(c, err);
+        if (rc != RLBM_OK) {
+            push_free(c);
+            return rc;
+        }
+    }
+    if (!c->pvalid) {
+        c->pcur = c->cur;
+        const hipError_t e = launch_push(c, true);
+        if (e != hipSuccess) {
+            err = hipGetErrorString(e);
+            return RLBM_EDEVICE;
+        }
+        c->pvalid = 1;
+    }
+    return RLBM_OK;
+}
+
+int push_batch_wgs(rlbm_ctx c) { return ((c->nx + 63) / 64) * ((c->ny + 3) / 4); }
+
+int push_batch_descs(const std::vector<rlbm_ctx>& cs, void** d_descs, int* total_wgs)
+{
+    std::vector<PushDesc> d(cs.size());
+    int wg = 0;
+    for (size_t i = 0; i < cs.size(); ++i) {
+        rlbm_ctx c = cs[i];
+        d[i].f[0] = c->f[0];
+        d[i].f[1] = c->f[1];
+        d[i].pp[0] = c->pp[0];
+        d[i].pp[1] = c->pp[1];
+        d[i].P = make_push_params(c);
+        d[i].wg0 = wg;
+        d[i].wgs = push_batch_wgs(c);
+        wg += d[i].wgs;
+    }
+    *total_wgs = wg;
+    *d_descs = nullptr;
+    if (d.empty()) return RLBM_OK;
+    if (hipMalloc(d_descs, d.size() * sizeof(PushDesc)) != hipSuccess) return RLBM_ENOMEM;
+    if (hipMemcpy(*d_descs, d.data(), d.size() * sizeof(PushDesc), hipMemcpyHostToDevice) != hipSuccess)
+        return RLBM_EDEVICE;
+    return RLBM_OK;
+}
+
+// One step of all push-kernel problems of a batch (buffers of parity
+// `parity` in, the other out).
+hipError_t launch_push_batch(int prec, int nmax, const void* d_descs, int nprob, int total_wgs, int parity,
+                             hipStream_t st)
+{
+    if (nprob < 1 || total_wgs < 1) return hipSuccess;
+    if (prec == RLBM_F32) {
+        if (nmax == 3) return launch_push_batch_t<float, 3>(d_descs, nprob, total_wgs, parity, st);
+        if (nmax == 5) return launch_push_batch_t<float, 5>(d_descs, nprob, total_wgs, parity, st);
+        return launch_push_batch_t<float, 7>(d_descs, nprob, total_wgs, parity, st);
+    }
+    if (nmax == 3) return launch_push_batch_t<double, 3>(d_descs, nprob, total_wgs, parity, st);
+    if (nmax == 5) return launch_push_batch_t<double, 5>(d_descs, nprob, total_wgs, parity, st);
+    return launch_push_batch_t<double, 7>(d_descs, nprob, total_wgs, parity, st);
 }

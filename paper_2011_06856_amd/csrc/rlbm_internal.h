@@ -279,6 +279,11 @@ hipError_t launch_batch_flat(int prec, int nmax, int waves, int items, const Bat
 void push_free(rlbm_ctx c);
 int push_setup(rlbm_ctx c, std::string& err);
 hipError_t launch_push(rlbm_ctx c, bool init);
+int push_prepare(rlbm_ctx c, std::string& err);
+int push_batch_wgs(rlbm_ctx c);
+int push_batch_descs(const std::vector<rlbm_ctx>& cs, void** d_descs, int* total_wgs);
+hipError_t launch_push_batch(int prec, int nmax, const void* d_descs, int nprob, int total_wgs, int parity,
+                             hipStream_t st);
 // Kernel used by rlbm_step for this context (resolves RLBM_KERNEL_AUTO).
 int resolve_kernel(rlbm_ctx c);
 int batch_grid(int prec, int nmax, int waves, int max_np);

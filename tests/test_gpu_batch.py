@@ -122,3 +122,27 @@ def test_autotune_keeps_state_and_picks_a_candidate(tmp_path):
     ref.step(2)
     for i in range(len(b)):
         assert np.array_equal(b.problem(i).get_populations(), ref.problem(i).get_populations())
+
+
+def test_batch_with_push_kernel_problems_equals_single_runs_bitwise():
+    """Problems with many velocities take the push kernel inside the batch
+    (one extra flat launch per step); each still evolves exactly as when
+    stepped alone, in both launch modes of the tile part."""
+    rl = _rlbm()
+    probs = small_problems(5, count=4)
+    for i, K in ((1, 96), (3, 128)):        # 384 and 512 velocities: push kernel
+        probs[i] = dict(probs[i], K=K)
+    for prec in ("f32", "f64"):
+        for mode in ("persistent", "flat"):
+            b = rl.Batch(probs, precision=prec)
+            b.set_mode(mode)
+            waves = b.get_waves()
+            say("batch+push %s %s waves=%d" % (prec, mode, waves))
+            b.step(5)
+            for i, p in enumerate(probs):
+                s = rl.Solver(p["Np"], p["K"], p["N"]).init_fields(p["nx"], p["ny"], *p["fields"], tau=p["tau"],
+                                                                   dt=p["dt"], precision=prec)
+                assert s.get_kernel() == ("push" if p["K"] >= 96 else "tile")
+                s.set_waves(waves)
+                s.step(5)
+                assert np.array_equal(b.problem(i).get_populations(), s.get_populations()), (prec, mode, i)
