@@ -1,0 +1,25 @@
+"""GPU test of the accuracy-study driver (Sec. 3.1): on a reduced tube, the
+error of the velocity profile saturates at a small population count in the
+near-hydrodynamic regime (about 100 populations at Kn = 0.05) and keeps
+falling with the population count in the near-ballistic one (Kn = 10), the
+behaviour Sec. 3.1 reports for its Fig. 3."""
+import sys
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def test_tube_error_depends_on_angles_only_beyond_hydro():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2011_06856_amd import studies
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    res = studies.tube_study(Kns=(0.05, 10.0), Ks=(8, 24, 96), L=400, refine=2, K_ref=240, log=log)
+    lo, hi = res[0.05]["eps"], res[10.0]["eps"]
+    log("Kn 0.05: %s  Kn 10: %s" % (lo, hi))
+    # N_pop = 32, 96, 384
+    assert lo[1] < 1.2 * lo[2]                               # Kn 0.05: saturated by N_pop ~ 100
+    assert res[0.05]["saturation_npop"] <= 96
+    assert hi[0] > hi[1] > 2 * hi[2]                         # Kn 10: still falling beyond 96
