@@ -10,6 +10,8 @@ grid, across Knudsen numbers.
   480 over a range of grid sizes, against N_pop = 2400 on the finest grid.
 - square_study (Sec. 3.2, Fig. 6): the 2D quadrant problem of Sec. 3.2 on
   L x L cells (clamped), against K = 600 on a grid refined by `refine`.
+- fig5_study (Sec. 3.2, Fig. 5): that problem with K = 600 on 1000 x 1000
+  against K = 12 on 500 x 500, at Kn = 0.002, 0.1 and 100.
 
 The error is Eq. rel_err: || beta - beta_ref ||_2 / || beta_ref ||_2 with
 beta = U / U^0 (both components in 2D), taken at t = 0.9 t_max, t_max = L / 2
@@ -46,8 +48,9 @@ import workloads as W  # noqa: E402
 NP = 4   # shells of the order-3 quadrature (N + 1)
 
 
-def run(fields, nx, ny, K, Kn, precision="f64", bc=(1, 1), Np=NP):
-    """Advance the state to t = 0.9 t_max and return beta = (bx, by)."""
+def run(fields, nx, ny, K, Kn, precision="f64", bc=(1, 1), Np=NP, with_density=False):
+    """Advance the state to t = 0.9 t_max and return beta = (bx, by) (and the
+    density with `with_density`)."""
     from paper_2011_06856_amd import rlbm
     L = nx
     tau = W.tau_of(Kn, L)
@@ -63,7 +66,8 @@ def run(fields, nx, ny, K, Kn, precision="f64", bc=(1, 1), Np=NP):
     finally:
         del s
     g = np.sqrt(1.0 + ux * ux + uy * uy)
-    return np.stack([ux / g, uy / g])
+    beta = np.stack([ux / g, uy / g])
+    return (beta, n[None]) if with_density else beta
 
 
 def restrict(beta, r, two_d):
@@ -140,6 +144,27 @@ def square_study(Kns=(0.05, 0.5, 2.0, 10.0), Ks=(8, 12, 18, 24, 36, 48, 60, 75, 
     return out
 
 
+def fig5_study(Kns=(0.002, 0.1, 100.0), L_fine=1000, K_fine=600, L_coarse=500, K_coarse=12, precision="f32",
+               log=print):
+    """Sec. 3.2, Fig. 5: the 2D quadrant problem at 0.9 t_max with K = 600 on
+    1000 x 1000 and K = 12 on 500 x 500; the relative L2 differences of the
+    density and of beta after averaging the fine solution onto the coarse
+    grid.  The paper finds the two in agreement in the hydrodynamic regime
+    and the coarse stencil's artefacts growing with Kn."""
+    out = {}
+    r = L_fine // L_coarse
+    for Kn in Kns:
+        t0 = time.perf_counter()
+        fine = run(W.paper_quadrant(L_fine, L_fine), L_fine, L_fine, K_fine, Kn, precision, with_density=True)
+        coarse = run(W.paper_quadrant(L_coarse, L_coarse), L_coarse, L_coarse, K_coarse, Kn, precision,
+                     with_density=True)
+        fb, fn = restrict(fine[0], r, True), restrict(fine[1], r, True)
+        out[Kn] = dict(density=rel_err(coarse[1], fn), beta=rel_err(coarse[0], fb))
+        log("fig5 Kn=%g: density %.3g beta %.3g (%.1f s)" % (Kn, out[Kn]["density"], out[Kn]["beta"],
+                                                              time.perf_counter() - t0))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true", help="smaller grids and sweeps")
@@ -152,7 +177,8 @@ def main():
         res = dict(tube=tube_study(Kns=(0.05, 10.0), Ks=(8, 24, 96), L=400, K_ref=240, log=say),
                    square=square_study(Kns=(0.05, 10.0), Ks=(8, 24, 96), L=64, refine=2, K_ref=240, log=say))
     else:
-        res = dict(tube=tube_study(log=say), convergence=convergence_study(log=say), square=square_study(log=say))
+        res = dict(tube=tube_study(log=say), convergence=convergence_study(log=say), square=square_study(log=say),
+                   fig5=fig5_study(log=say))
     if a.out:
         json.dump(res, open(a.out, "w"), indent=1, default=float)
 
