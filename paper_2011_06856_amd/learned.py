@@ -109,7 +109,7 @@ def collect(side, seeds, K_coarse, K_fine, steps, snapshots, rows_per_snapshot, 
     return np.concatenate(X), np.concatenate(T)
 
 
-def collect(side, seeds, K_coarse, K_fine, steps, snapshots, rows_per_snapshot, net=None, seed_rows=0):
+def collect(side, seeds, K_coarse, K_fine, steps, snapshots, rows_per_snapshot, net=None, seed_rows=0, log=None):
     """Training rows, teacher-forced.  A fine and a coarse run start from the
     same state and step in lockstep; after every coarse step its shear stress
     is set to the fine run's (the exact correction, added through the m = 2
@@ -124,7 +124,9 @@ def collect(side, seeds, K_coarse, K_fine, steps, snapshots, rows_per_snapshot, 
     snap = set(int(round(steps * (k + 1) / snapshots)) for k in range(snapshots))
     ident = rlbm.MLP(max_batch=side * side, n_hidden=1, hidden=8)   # feature kernel with unit scales
     ident.set_norm(np.zeros(7), np.ones(7), np.zeros(3), np.ones(3))
-    for sd in seeds:
+    for si, sd in enumerate(seeds):
+        if log and si % 20 == 0:
+            log("learned: collecting seed %d of %d" % (si, len(seeds)))
         Kn, fld, tau, dt = shock(side, sd)
         f = make_solver(K_fine, side, fld, tau, dt)
         c = make_solver(K_coarse, side, fld, tau, dt)
@@ -166,6 +168,7 @@ class Normaliser:
 
 
 def train(net, Xn, Tn, epochs=20, batch=4096, lr=1e-3, seed=0, log=None):
+    """Mini-batch Adam over shuffled rows; returns the mean loss per epoch."""
     import torch
     Xd = torch.as_tensor(Xn, device="cuda")
     Td = torch.as_tensor(Tn, device="cuda")
@@ -282,14 +285,14 @@ def study(side=512, K_coarse=24, K_fine=384, steps=230, train_seeds=range(200), 
     import torch
     say = log or (lambda m: None)
     t0 = time.perf_counter()
-    X, T = collect(side, list(train_seeds), K_coarse, K_fine, steps, snapshots, rows)
+    X, T = collect(side, list(train_seeds), K_coarse, K_fine, steps, snapshots, rows, log=say)
     say("learned: %d training rows in %.1f s" % (X.shape[0], time.perf_counter() - t0))
     nm = Normaliser(X, T)
     net = rlbm.MLP(max_batch=side * side)
     net.init_params(seed=1)
     nm.apply(net)
     t1 = time.perf_counter()
-    losses = train(net, nm.inputs(X), nm.targets(T), epochs=epochs, batch=batch, lr=lr)
+    losses = train(net, nm.inputs(X), nm.targets(T), epochs=epochs, batch=batch, lr=lr, log=say)
     for r in range(dagger):
         seeds = [100000 + 1000 * r + k for k in range(len(list(train_seeds)) // 4)]
         X2, T2 = collect(side, seeds, K_coarse, K_fine, steps, snapshots, rows, net=net, seed_rows=r + 1)
