@@ -56,7 +56,6 @@ template <typename T, int NM>
 int upload_tables_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, long long S, int precision)
 {
     const size_t nv = c->q.nvel, npad = nv + RLBM_VPAD;
-    const long long es = (long long)elem_size(precision);
     std::vector<SRec<T>> sr(npad);
     std::vector<CRec<T, NM>> cr(npad);
     for (size_t v = 0; v < npad; ++v) {
@@ -65,10 +64,6 @@ int upload_tables_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, long long
         CRec<T, NM>& B = cr[v];
         std::memset(&A, 0, sizeof(A));
         std::memset(&B, 0, sizeof(B));
-        A.roff = real ? (long long)v * S * es : 0;
-        A.dx = real ? (vd[v].sx > 0 ? -1 : 1) * (int)es : -(int)es;
-        A.sy = real ? (vd[v].sy > 0 ? 1 : -1) : 1;
-        B.woff = (long long)(real ? v : nv) * S * es;
         B.shell = real ? (int)(v / c->q.K) : c->q.Np - 1;
         if (!real) continue;
         const VelRec<double>& R = vd[v];

@@ -109,16 +109,35 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
     char* const outb = reinterpret_cast<char*>(fout) + rowb;
     const int v0 = w * P.chunk;
     const int nbatch = min(P.chunk, VPT) / LB;   // batches held in registers
+    // plane offsets: velocity v reads its plane (a null entry the last
+    // velocity's) and writes its plane (a null entry the spare one)
+    const long long pbytes = P.S * (long long)ES;
+    auto rplane = [&](int v) __attribute__((always_inline)) -> long long { return (long long)min(v, P.nvel - 1) * pbytes; };
+    auto wplane = [&](int v) __attribute__((always_inline)) -> long long { return (long long)min(v, P.nvel) * pbytes; };
+    // the held slots run through consecutive planes: running plane pointers
+    const char* const rlast = inb + rplane(P.nvel);
+    const char* rcur = inb + (long long)v0 * pbytes;
+    auto rnext = [&](int v) __attribute__((always_inline)) -> const char* {
+        const char* p = v < P.nvel ? rcur : rlast;
+        rcur += pbytes;
+        return p;
+    };
+    // upwind signs from the sign bits of the moment rows p c and p s
+    auto xneg = [](TC pc) __attribute__((always_inline)) -> bool {
+        return (__builtin_bit_cast(std::conditional_t<sizeof(TC) == 8, unsigned long long, unsigned>, pc) >>
+                (sizeof(TC) * 8 - 1)) != 0;
+    };
 
     auto ld = [](const char* base, unsigned off) __attribute__((always_inline)) -> TC { return (TC)*reinterpret_cast<const TS*>(base + off); };
-    auto load4 = [&](auto fast, int v, TC* r) __attribute__((always_inline)) {
+    auto load4 = [&](auto fast, int v, const char* p0, TC* r) __attribute__((always_inline)) {
         CSRec& M = srec[v];
-        const char* p0 = inb + M.roff;
-        const char* p1 = p0 + (M.sy > 0 ? dmb : dpb);
+        const bool cneg = xneg(M.P[1]);   // upwind column x + 1
+        const char* p1 = p0 + (xneg(M.P[2]) ? dpb : dmb);
         if (decltype(fast)::value) {
-            r[0] = ld(p0, ocb); r[1] = ld(p0 + M.dx, ocb); r[2] = ld(p1, ocb); r[3] = ld(p1 + M.dx, ocb);
+            const int dx = cneg ? (int)ES : -(int)ES;
+            r[0] = ld(p0, ocb); r[1] = ld(p0 + dx, ocb); r[2] = ld(p1, ocb); r[3] = ld(p1 + dx, ocb);
         } else {
-            const unsigned osb = M.dx < 0 ? omb : opb;
+            const unsigned osb = cneg ? opb : omb;
             r[0] = ld(p0, ocb); r[1] = ld(p0, osb); r[2] = ld(p1, ocb); r[3] = ld(p1, osb);
         }
     };
@@ -138,7 +157,7 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
             if (kb < nbatch) {
                 TC raw[LB][4];
 #pragma unroll
-                for (int b = 0; b < LB; ++b) load4(fast, v0 + kb * LB + b, raw[b]);
+                for (int b = 0; b < LB; ++b) load4(fast, v0 + kb * LB + b, rnext(v0 + kb * LB + b), raw[b]);
 #pragma unroll
                 for (int b = 0; b < LB; ++b) {
                     const int v = v0 + kb * LB + b;
@@ -152,7 +171,7 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
         }
         for (int v = v0 + VPT; v < v0 + P.chunk; ++v) {
             TC r[4];
-            load4(fast, v, r);
+            load4(fast, v, inb + rplane(v), r);
             const TC f = bilin(v, r);
             CSRec& R = srec[v];
 #pragma unroll
@@ -205,7 +224,14 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
     TC cc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) cc[t] = coef[(shell * NT + t) * 64 + lane];
-    auto collide = [&](auto fast, int v, TC f) __attribute__((always_inline)) {
+    char* wcur = outb + (long long)v0 * pbytes;
+    char* const wspare = outb + wplane(P.nvel);
+    auto wnext = [&](int v) __attribute__((always_inline)) -> char* {
+        char* p = v < P.nvel ? wcur : wspare;
+        wcur += pbytes;
+        return p;
+    };
+    auto collide = [&](auto fast, int v, char* wbase, TC f) __attribute__((always_inline)) {
         CCRec& R = crec[v];
         if (R.shell != shell) {
             shell = R.shell;
@@ -217,7 +243,7 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
         for (int t = 1; t < NT; ++t) feq += cc[t] * R.H[t];
         const TC om_ = a0 - ax * R.cth - ay * R.sth;
         const TC fn = f + om_ * (feq - f);
-        TS* dst = reinterpret_cast<TS*>(outb + R.woff + ocb);
+        TS* dst = reinterpret_cast<TS*>(wbase + ocb);
         // non-temporal: the next read of this plane is a step away
 #ifndef RLBM_TEMPORAL_STORE
         if (decltype(fast)::value || active) __builtin_nontemporal_store((TS)fn, dst);
@@ -230,13 +256,13 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
         for (int kb = 0; kb < VPT / LB; ++kb) {
             if (kb < nbatch) {
 #pragma unroll
-                for (int b = 0; b < LB; ++b) collide(fast, v0 + kb * LB + b, fs[kb * LB + b]);
+                for (int b = 0; b < LB; ++b) collide(fast, v0 + kb * LB + b, wnext(v0 + kb * LB + b), fs[kb * LB + b]);
             }
         }
         for (int v = v0 + VPT; v < v0 + P.chunk; ++v) {
             TC r[4];
-            load4(fast, v, r);
-            collide(fast, v, bilin(v, r));
+            load4(fast, v, inb + rplane(v), r);
+            collide(fast, v, outb + wplane(v), bilin(v, r));
         }
     };
     if (interior)

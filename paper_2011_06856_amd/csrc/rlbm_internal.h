@@ -33,41 +33,38 @@ struct alignas(16) VelRec {
 };
 static_assert(sizeof(VelRec<float>) == 32 * 4, "VelRec layout");
 
-// Per-velocity records of the fused kernel, one per phase, each read with a
-// single wave-uniform scalar load.  The tables are padded past nvel with null
-// entries (zero weights, zero equilibrium row, reads from plane 0, writes to
-// the spare plane at the end of each buffer, last shell) so that every wave
-// processes whole load batches without range checks.
+// Per-velocity records of the fused kernel, one per phase, read with
+// wave-uniform scalar loads.  The tables are padded past nvel with null
+// entries (zero weights, zero equilibrium row, last shell) so that every wave
+// processes whole load batches without range checks; a null entry reads the
+// last velocity's plane and writes the spare plane at the end of each buffer.
+// The records hold only what the plane index v does not give (the plane
+// offsets are v times the plane size, the upwind signs are those of P[1] and
+// P[2]), so that the tables of a velocity set stay in the scalar cache.
 //
 // Streaming record (phase 1):
 //   w[4]   bilinear weights of the cells (x,y) (x-sx,y) (x,y-sy) (x-sx,y-sy):
 //          (1-ax)(1-ay), ax(1-ay), (1-ax)ay, ax ay, ax = dt|cos|, ay = dt|sin|
 //   P[]    moment rows p, p c, p s, p^2, p^2 c, p^2 s, p^2 c^2, p^2 c s
-//          (and p^2 s^2 in FP64; FP32 takes T^yy = T^00 - T^xx)
-//   roff   byte offset of the velocity's plane in the input buffer
-//   dx     byte shift to the upwind column, -sgn(cos th) * element size
-//   sy     upwind row sign sgn(sin th) as +-1 (sgn 0 = +1)
+//          (and p^2 s^2 in FP64; FP32 takes T^yy = T^00 - T^xx); the sign
+//          bits of P[1] and P[2] are those of cos and sin (sx, sy; sgn 0 = +1)
 template <typename T>
-struct alignas(sizeof(T) == 8 ? 128 : 64) SRec {
+struct alignas(16) SRec {
     T w[4];
     T P[sizeof(T) == 8 ? 9 : 8];
-    long long roff;
-    int dx, sy;
 };
-static_assert(sizeof(SRec<float>) == 64 && sizeof(SRec<double>) == 128, "SRec layout");
+static_assert(sizeof(SRec<float>) == 48 && sizeof(SRec<double>) == 112, "SRec layout");
 
 // Collision record (phase 4):
 //   H[2NM+1]  w_v {1, cos th, sin th, ..., cos NM th, sin NM th}: f_eq_v is
 //             sum_t coef_shell[t] H[t] (zero above the expansion order)
 //   cth sth   direction n_v (collision frequency U^0 - U.n_v)
-//   woff      byte offset of the velocity's plane in the output buffer
 //   shell     radial shell index i
 template <typename T, int NM>
 struct alignas(16) CRec {
     T H[2 * NM + 1];
     T cth, sth;
-    long long woff;
-    int shell, pad;
+    int shell;
 };
 
 // Velocities per load batch and the padding of the velocity tables.
