@@ -83,10 +83,16 @@ struct PushParams {
     const double* G;
     const double* Pc;
     int nx, ny, Np, bcx, bcy, ntiles;
+    int nrec;                // records in the tables (all segments)
     long long S;
     double rate, dt;
     int* flag;
 };
+
+// Scalar-cache prefetch distance of the push kernel, in load batches (0: off).
+#ifndef RLBM_PUSH_PREFETCH
+#define RLBM_PUSH_PREFETCH 2
+#endif
 
 constexpr int NMOM = 8;     // N^0 N^x N^y T^00 T^0x T^0y T^xx T^xy
 
@@ -259,6 +265,20 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
                 for (int j = 0; j < 9; ++j) Sm[j] = T(0);
                 const int v0 = G.begin;
                 for (int kb = 0; kb < G.nbatch; ++kb) {
+                    // the records RLBM_PUSH_PREFETCH batches on (the table runs
+                    // on across segments): one word of each scalar-cache line,
+                    // taken in only at the end of this batch
+                    unsigned pf = 0;
+                    if (RLBM_PUSH_PREFETCH > 0) {
+                        const int ahead = min(v0 + (kb + RLBM_PUSH_PREFETCH) * LB, P.nrec - LB);
+                        using CWord = const PUSH_CONST_AS unsigned;
+                        const PUSH_CONST_AS char* rb = (const PUSH_CONST_AS char*)(rec + ahead);
+                        constexpr int RB = LB * (int)sizeof(PRec<T, NM>);
+#pragma unroll
+                        for (int o = 0; o < RB; o += 64) pf += *(CWord*)(rb + o);
+                        pf += *(CWord*)(rb + RB - 4);
+                        pf += *(CWord*)((const PUSH_CONST_AS char*)(adr + ahead));
+                    }
                     // LB velocities' loads in flight, then their arithmetic
                     T raw[LB][4];
 #pragma unroll
@@ -309,6 +329,7 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
 #pragma unroll
                         for (int j = 0; j < 8; ++j) Sm[1 + j] = fma(fnew, (T)Rr.mono[j], Sm[1 + j]);
                     }
+                    if (RLBM_PUSH_PREFETCH > 0) asm volatile("" ::"s"(pf));
                 }
                 // fold the monomial sums into the weighted moment sums of the
                 // segment's four corners: with T_e = sum f e, the corner sums
@@ -542,6 +563,7 @@ int upload_push_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, int precisi
         err = "push table size";
         return RLBM_EINVAL;
     }
+    c->pnrec = (int)recs.size();
     hipError_t e;
     if ((e = hipMalloc(&c->d_prec, recs.size() * sizeof(PRec<T, NM>))) != hipSuccess) return RLBM_ENOMEM;
     if ((e = hipMalloc(&c->d_paddr, adrs.size() * sizeof(PAddr))) != hipSuccess) return RLBM_ENOMEM;
@@ -616,6 +638,7 @@ PushParams make_push_params(rlbm_ctx c)
     P.Pc = c->d_Pc;
     P.nx = c->nx; P.ny = c->ny; P.Np = c->q.Np; P.bcx = c->bcx; P.bcy = c->bcy;
     P.ntiles = ((c->nx + 63) / 64) * c->ny;
+    P.nrec = c->pnrec;
     P.S = c->S;
     P.rate = c->rate;
     P.dt = c->dt;

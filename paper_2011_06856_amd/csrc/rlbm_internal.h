@@ -252,6 +252,7 @@ struct rlbm_ctx_s {
     void* d_pseg = nullptr;
     void* pp[2] = {nullptr, nullptr};
     int pcur = 0;
+    int pnrec = 0;                       // records in the push tables
     int pvalid = 0;                      // pp[pcur] holds the partial sums of f[cur]
 };
 
