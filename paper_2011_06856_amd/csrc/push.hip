@@ -84,10 +84,29 @@ struct PushParams {
     const double* Pc;
     int nx, ny, Np, bcx, bcy, ntiles;
     int nrec;                // records in the tables (all segments)
+    int sb;                  // bands of 4 rows taken column by column (work-group order)
     long long S;
     double rate, dt;
     int* flag;
 };
+
+// Work-group order of the push kernel: groups of RLBM_PUSH_SB bands of 4
+// rows are taken column by column, so that vertically adjacent work-groups
+// (whose boundary rows are each other's upwind rows) run at the same time.
+#ifndef RLBM_PUSH_SB
+#define RLBM_PUSH_SB 2
+#endif
+
+// Band (of 4 rows) and tile column of work-group b in that order.
+__device__ __forceinline__ void push_wg_tile(int b, int ntx, int ny, int sb, int& band, int& col)
+{
+    const int nb = (ny + 3) >> 2;
+    const int g = b / (sb * ntx);
+    const int sbg = min(sb, nb - g * sb);   // bands in this group
+    const int r = b - g * sb * ntx;
+    band = g * sb + r % sbg;
+    col = r / sbg;
+}
 
 // Scalar-cache prefetch distance of the push kernel, in load batches (0: off).
 #ifndef RLBM_PUSH_PREFETCH
@@ -422,11 +441,12 @@ __global__ __launch_bounds__(256, RLBM_PUSH_WPE) void k_push_step(const T* __res
     // reuse; one grid row of all velocities is far larger than the L2).
     const int ntx = (P.nx + 63) >> 6;
     const int b = xcd_remap_p(blockIdx.x, gridDim.x);
-    const int band = b / ntx;
+    int band, col;
+    push_wg_tile(b, ntx, P.ny, P.sb, band, col);
     const int ty = band * 4 + wv;
     if (ty >= P.ny) return;   // whole waves; the kernel has no barrier
     const bool live = true;
-    const int tile = ty * ntx + (b - band * ntx);
+    const int tile = ty * ntx + col;
     T* lh = reinterpret_cast<T*>(psmem) + (size_t)wv * (96 + 3 * NMOM * 64);
     push_tile<T, NM, LB, INIT>(fin, fout, pin, pout, P, tile, lh, live);
 }
@@ -458,10 +478,11 @@ __global__ __launch_bounds__(256, RLBM_PUSH_WPE) void k_push_batch(const PushDes
     const PushParams P = D.P;
     const int ntx = (P.nx + 63) >> 6;
     const int b = g - D.wg0;
-    const int band = b / ntx;
+    int band, col;
+    push_wg_tile(b, ntx, P.ny, P.sb, band, col);
     const int ty = band * 4 + wv;
     if (ty >= P.ny) return;   // whole waves; the kernel has no barrier
-    const int tile = ty * ntx + (b - band * ntx);
+    const int tile = ty * ntx + col;
     T* lh = reinterpret_cast<T*>(psmem) + (size_t)wv * (96 + 3 * NMOM * 64);
     push_tile<T, NM, LB, false>(static_cast<const T*>(D.f[parity]), static_cast<T*>(D.f[parity ^ 1]),
                                 static_cast<const T*>(D.pp[parity]), static_cast<T*>(D.pp[parity ^ 1]), P, tile, lh,
@@ -639,6 +660,7 @@ PushParams make_push_params(rlbm_ctx c)
     P.nx = c->nx; P.ny = c->ny; P.Np = c->q.Np; P.bcx = c->bcx; P.bcy = c->bcy;
     P.ntiles = ((c->nx + 63) / 64) * c->ny;
     P.nrec = c->pnrec;
+    P.sb = RLBM_PUSH_SB;
     P.S = c->S;
     P.rate = c->rate;
     P.dt = c->dt;
