@@ -25,6 +25,6 @@ run() {   # name, kernel, launch bytes, stats args, counter args
         --command "rocprofv3 --kernel-trace --stats -- python3 -m paper_2011_06856_amd.profile_run $sargs ; rocprofv3 --pmc FETCH_SIZE -- python3 -m paper_2011_06856_amd.profile_run $cargs ; rocprofv3 --pmc WRITE_SIZE -- python3 -m paper_2011_06856_amd.profile_run $cargs (bash paper_2011_06856_amd/profile_all.sh)"
 }
 # algorithmic bytes per launch: 8 B per site-velocity (FP32 read + write)
-run stream_collide_f32_circular_1024 "k_stream_collide<float, float, 3, 64>" 2147483648 "--steps 20" "--steps 4"
+run stream_collide_f32_circular_1024 "k_stream_collide<float, float, 3, 64>" 2147483648 "--steps 200" "--steps 4"
 run push_step_f32_quadrant_2048 "k_push_step<float, 5, 8, false>" 51539607552 \
-    "--workload quadrant --side 2048 --steps 6" "--workload quadrant --side 2048 --steps 3"
+    "--workload quadrant --side 2048 --steps 20" "--workload quadrant --side 2048 --steps 3"
