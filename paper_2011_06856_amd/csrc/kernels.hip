@@ -41,6 +41,17 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
     return k * q + min(k, r) + j;
 }
 
+// Sum of one word of each 64-byte scalar-cache line of [p, p + BYTES): read
+// to bring those lines into the scalar cache ahead of their use.
+template <int BYTES>
+__device__ __forceinline__ unsigned touch_lines(const RLBM_CONST_AS char* p)
+{
+    unsigned s = 0;
+#pragma unroll
+    for (int o = 0; o < BYTES; o += 64) s += *(const RLBM_CONST_AS unsigned*)(p + o);
+    return s;
+}
+
 __device__ __forceinline__ int wrap_idx(int i, int n, int bc)
 {
     if (bc == RLBM_BC_PERIODIC) {
@@ -255,8 +266,15 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
 #pragma unroll
         for (int kb = 0; kb < VPT / LB; ++kb) {
             if (kb < nbatch) {
+                // the next batch's collision records: one word of each
+                // scalar-cache line now, taken in only after this batch (the
+                // records of the work-group's velocities do not all stay
+                // cached between the phases)
+                const unsigned pf = touch_lines<LB * (int)sizeof(CRec<TC, NM>)>(
+                    (const RLBM_CONST_AS char*)(crec + min(v0 + (kb + 1) * LB, P.nvel + RLBM_VPAD - LB)));
 #pragma unroll
                 for (int b = 0; b < LB; ++b) collide(fast, v0 + kb * LB + b, wnext(v0 + kb * LB + b), fs[kb * LB + b]);
+                asm volatile("" ::"s"(pf));
             }
         }
         for (int v = v0 + VPT; v < v0 + P.chunk; ++v) {
