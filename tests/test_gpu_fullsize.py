@@ -104,3 +104,34 @@ def test_quadrant_full_size_sampled_sites():
     cfg = W.quadrant_shock(2048, steps=STEPS)
     pts = samples(2048, 2048, [(1023, 1024), (1024, 1023), (1024, 1024), (0, 1024), (1024, 2047)], seed=4)
     check_sites(rl, cfg, "f32", 1e-4, pts, "quadrant_2048")
+
+
+def test_batch_full_size_sampled_sites():
+    """The 48-problem batch (sides 128..1024, Kn 1e-3..10, K 48..128, FP32)
+    in one launch per kernel per step: sampled sites of the two largest
+    problems, one of each kernel, and one of the smallest."""
+    import torch
+    rl = _rlbm()
+    probs = W.batch_problems(48, seed=0, steps=STEPS)
+    b = rl.Batch(probs, precision="f32")
+    say("case batch48 mode=%s waves=%d" % (b.get_mode(), b.get_waves()))
+    b.step(STEPS)
+    by_size = sorted(range(len(probs)), key=lambda i: probs[i]["nx"] * probs[i]["K"])
+    tile = [i for i in by_size if 4 * probs[i]["K"] < 320]
+    push = [i for i in by_size if 4 * probs[i]["K"] >= 320]
+    pick = sorted({by_size[-1], by_size[-2], by_size[0]} | ({tile[-1]} if tile else set()) |
+                  ({push[-1]} if push else set()))
+    worst = 0.0
+    for i in pick:
+        p = probs[i]
+        n, eps, ux, uy, _ = b.problem(i).moments()
+        pts = samples(p["nx"], p["ny"], [(p["nx"] // 2, p["ny"] // 2)], seed=10 + i)
+        for (x, y) in pts:
+            rn, reps, rux, ruy = oracle_at(p, x, y)
+            e = max(abs(n[y, x] - rn) / abs(rn), abs(eps[y, x] - reps) / abs(reps),
+                    np.hypot(ux[y, x] - rux, uy[y, x] - ruy) / np.sqrt(1.0 + 2.0 * (rux * rux + ruy * ruy)))
+            worst = max(worst, e)
+            assert e <= 1e-4, (i, p["nx"], p["K"], x, y, e)
+    say("batch48: problems %s, worst relative error %.3e" % (pick, worst))
+    del b
+    torch.cuda.empty_cache()
