@@ -220,8 +220,9 @@ def main():
     ap.add_argument("--tune-cache", action="store_true", help="reuse/store the autotuner choice in _tune_cache.json")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path "
+              "(the step would shard by row slabs with a one-row halo exchange per step); run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"

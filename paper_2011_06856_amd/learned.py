@@ -16,7 +16,7 @@ HIP kernels; numpy only samples and normalises training rows on the host):
 2. training: mini-batch Adam on the GPU (rlbm_mlp_grad, rlbm_mlp_adam_step).
 3. use: after every coarse step, rlbm_mlp_correct adds the predicted change
    of the stress to the populations (conserving N^mu and T^0mu).
-4. judge: the plain fine-angle solver; errors are Eq. rel_err per field; the
+4. reference: the plain fine-angle solver; errors are Eq. rel_err per field; the
    equal-error angle count K* of the plain solver, by log-log interpolation
    over a sweep of K, gives the speedup wall(plain K*) / wall(coarse + MLP).
 """

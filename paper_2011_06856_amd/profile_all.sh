@@ -8,7 +8,7 @@
 # GPU machine:  bash paper_2011_06856_amd/profile_all.sh OUT_DIR
 # Writes OUT_DIR/raw/... (rocprofv3 CSV) and OUT_DIR/<name>.md/.json.
 set -e
-OUT=${1:-gpurun_out/profiles}
+OUT=${1:-profile_out}
 ROOT=$(pwd)
 export TMPDIR=/tmp
 run() {   # name, kernel, launch bytes, stats args, counter args

@@ -82,7 +82,7 @@ def main():
     avg_ns = float(kstat[0]["AverageNs"]) if kstat else None
 
     lines = ["# %s" % a.name, "",
-             "Command (run from the repository root on the GPU box):", "", "```", a.command, "```", "",
+             "Command (run from the repository root on a machine with the GPU):", "", "```", a.command, "```", "",
              "## Kernel trace (rocprofv3 --kernel-trace --stats)", "",
              "| kernel | calls | avg us | min us | max us | % |", "|---|---|---|---|---|---|"]
     for r in sorted(stats, key=lambda r: -float(r["Percentage"])):
