@@ -271,7 +271,8 @@ int rlbm_mlp_get_grad(rlbm_mlp m, float* host);          /* last rlbm_mlp_grad r
 
 /* Feature and output scales of the correction: network input k of a site is
  * (field - in_mu[k]) / in_sig[k] for the 7 fields (n, eps, U^x, U^y, pi^xx,
- * pi^xy, pi^yy); the stress change is out_mu + out_sig * output. */
+ * pi^xy, pi^yy); output j is de-normalised as out_mu[j] + out_sig[j] * y_j
+ * (out_mu, out_sig: out_dim values each, out_dim <= 8). */
 int rlbm_mlp_set_norm(rlbm_mlp m, const float* in_mu, const float* in_sig, const float* out_mu, const float* out_sig);
 
 /* Device pointers: dX [B][in_dim], dY [B][out_dim], dT [B][out_dim]. */
@@ -300,6 +301,19 @@ int rlbm_mlp_features(rlbm_ctx c, rlbm_mlp m, float* dX);
  * Requires S <= max_batch and a shared stream.
  */
 int rlbm_mlp_correct(rlbm_ctx c, rlbm_mlp m, float scale, int relax);
+/*
+ * Readout correction of the macroscopic fields of a coarse-angle run (a
+ * network with out_dim = 4; the correction is to the fields of Eq. rel_err,
+ * not to the populations):
+ *   inputs   the features of rlbm_mlp_features with column 63 = extra (the
+ *            network is trained with a per-run scalar there, log10 Kn);
+ *   outputs  y (de-normalised with rlbm_mlp_set_norm's out_mu, out_sig);
+ *   fields   n (1 + y0), eps (1 + y1), U^x + y2, U^y + y3 of the current
+ *            populations, to host arrays [ny][nx] (caller-owned, any NULL).
+ * The populations are not changed.  Synchronous; RLBM_ENONPHYS as
+ * rlbm_moments; RLBM_EINVAL if out_dim != 4 or S > max_batch.
+ */
+int rlbm_mlp_readout(rlbm_ctx c, rlbm_mlp m, float extra, double* n, double* eps, double* ux, double* uy);
 /* The same change of the traceless stress from a device array [S][3] =
  * (dT^xx, dT^xy, dT^yy), times scale (e.g. to give a local-equilibrium state
  * a prescribed shear stress). */

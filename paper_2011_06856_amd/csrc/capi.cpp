@@ -349,6 +349,16 @@ int rlbm_moments(rlbm_ctx c, double* n, double* eps, double* ux, double* uy, dou
     hipError_t e = launch_fields(c->prec, c->f[c->cur], c->d_veld, c->d_fields, c->d_partials, c->d_flag, c->nx, c->ny,
                                  c->q.nvel, c->st);
     if (e != hipSuccess) return hip_fail(c, e, "fields launch");
+    return fields_out(c, n, eps, ux, uy, charges);
+}
+
+}  // extern "C"
+
+// Copy the fields computed into d_fields (and the charges) to the host,
+// synchronise, and report a non-physical state met since the last call.
+int fields_out(rlbm_ctx c, double* n, double* eps, double* ux, double* uy, double* charges)
+{
+    hipError_t e;
     const long long S = c->S;
     double* outs[4] = {n, eps, ux, uy};
     for (int k = 0; k < 4; ++k)
@@ -377,6 +387,8 @@ int rlbm_moments(rlbm_ctx c, double* n, double* eps, double* ux, double* uy, dou
     }
     return RLBM_OK;
 }
+
+extern "C" {
 
 int rlbm_populations_bytes(rlbm_ctx c, size_t* bytes)
 {

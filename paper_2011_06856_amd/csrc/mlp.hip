@@ -271,6 +271,30 @@ __global__ void k_patch(const float* __restrict__ stats, float* __restrict__ X, 
     o[63] = 0.f;
 }
 
+// Column 63 of the features: a per-run input (the readout network takes
+// log10 Kn there).
+__global__ void k_set_col63(float* __restrict__ X, long S, float v)
+{
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < S) X[s * 64 + 63] = v;
+}
+
+// Readout correction of the FP64 fields f = [n | eps | U^x | U^y] (each S):
+// with the de-normalised outputs y, n (1 + y0), eps (1 + y1), U^x + y2,
+// U^y + y3.
+__global__ void k_readout(double* __restrict__ f, const float* __restrict__ Y, const float* __restrict__ omu,
+                          const float* __restrict__ osig, long S)
+{
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    double y[4];
+    for (int k = 0; k < 4; ++k) y[k] = (double)(Y[s * 4 + k] * osig[k] + omu[k]);
+    f[s] *= 1.0 + y[0];
+    f[S + s] *= 1.0 + y[1];
+    f[2 * S + s] += y[2];
+    f[3 * S + s] += y[3];
+}
+
 // In-loop correction: the network output (de-normalised) is a traceless
 // stress (dTxx, dTxy, dTyy); its m = 2 part is put into the populations
 // through the orthonormal basis function p^2 {cos, sin}(2 th) / sqrt(24 pi),
@@ -343,7 +367,7 @@ struct rlbm_mlp_s {
     float* X = nullptr;   // features [maxb][in]
     float* stats = nullptr;
     double* partial = nullptr;
-    float* norm = nullptr;   // in_mu[7], in_sig[7], out_mu[3], out_sig[3]
+    float* norm = nullptr;   // in_mu[7], in_sig[7], out_mu[out], out_sig[out] (out <= 8)
     int adam_t = 0;
     std::string err;
 };
@@ -518,9 +542,9 @@ int rlbm_mlp_set_norm(rlbm_mlp m, const float* in_mu, const float* in_sig, const
         nrm[k] = in_mu[k];
         nrm[7 + k] = in_sig[k];
     }
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < m->out && k < 8; ++k) {
         nrm[14 + k] = out_mu[k];
-        nrm[17 + k] = out_sig[k];
+        nrm[14 + m->out + k] = out_sig[k];
     }
     hipError_t e = hipMemcpy(m->norm, nrm, sizeof(nrm), hipMemcpyHostToDevice);
     return e == hipSuccess ? RLBM_OK : mfail(m, RLBM_EDEVICE, hipGetErrorString(e));
@@ -627,6 +651,26 @@ int rlbm_mlp_correct(rlbm_ctx c, rlbm_mlp m, float scale, int relax)
     if ((rc = rlbm_mlp_forward(m, m->X, (int)c->S, m->Y)) != RLBM_OK) return rc;
     // w p^2 cos 2th and w p^2 sin 2th per velocity, from the FP64 table
     return add_stress(c, m->Y, m->norm + 14, m->norm + 17, relax ? m->stats : nullptr, scale);
+}
+
+// Readout correction of a context's fields: features with column 63 =
+// `extra`, forward pass, the fields of the current populations corrected by
+// the de-normalised outputs (k_readout), copied to the host.
+int rlbm_mlp_readout(rlbm_ctx c, rlbm_mlp m, float extra, double* n, double* eps, double* ux, double* uy)
+{
+    if (!c || !m || !c->have_fields) return RLBM_EINVAL;
+    if (m->out != 4) return mfail(m, RLBM_EINVAL, "the readout correction needs four outputs");
+    int rc = rlbm_mlp_features(c, m, m->X);
+    if (rc != RLBM_OK) return rc;
+    hipLaunchKernelGGL(k_set_col63, dim3(nblk(c->S)), dim3(256), 0, c->st, m->X, (long)c->S, extra);
+    if ((rc = rlbm_mlp_forward(m, m->X, (int)c->S, m->Y)) != RLBM_OK) return rc;
+    hipError_t e = launch_fields(c->prec, c->f[c->cur], c->d_veld, c->d_fields, c->d_partials, c->d_flag, c->nx, c->ny,
+                                 c->q.nvel, c->st);
+    if (e != hipSuccess) return mfail(m, RLBM_EDEVICE, hipGetErrorString(e));
+    hipLaunchKernelGGL(k_readout, dim3(nblk(c->S)), dim3(256), 0, c->st, c->d_fields, m->Y, m->norm + 14,
+                       m->norm + 18, (long)c->S);
+    if ((e = hipGetLastError()) != hipSuccess) return mfail(m, RLBM_EDEVICE, hipGetErrorString(e));
+    return fields_out(c, n, eps, ux, uy, nullptr);
 }
 
 // Add a change of the traceless stress, device [S][3] = (dT^xx, dT^xy,

@@ -282,6 +282,9 @@ int push_batch_wgs(rlbm_ctx c);
 int push_batch_descs(const std::vector<rlbm_ctx>& cs, void** d_descs, int* total_wgs);
 hipError_t launch_push_batch(int prec, int nmax, const void* d_descs, int nprob, int total_wgs, int parity,
                              hipStream_t st);
+// Copy the fields in d_fields (computed by launch_fields) and the charges to
+// the host and report a sticky non-physical state (capi.cpp).
+int fields_out(rlbm_ctx c, double* n, double* eps, double* ux, double* uy, double* charges);
 // Kernel used by rlbm_step for this context (resolves RLBM_KERNEL_AUTO).
 int resolve_kernel(rlbm_ctx c);
 int batch_grid(int prec, int nmax, int waves, int max_np);

@@ -77,38 +77,6 @@ def spatial_stress(stats):
     return torch.stack([w * ux * ux + P + stats[:, 4], w * ux * uy + stats[:, 5], w * uy * uy + P + stats[:, 6]], 1)
 
 
-def collect(side, seeds, K_coarse, K_fine, steps, snapshots, rows_per_snapshot, seed_rows=0):
-    """Training rows.  At snapshot steps t the fine state is restricted to the
-    coarse angle set (harmonics the coarse set resolves) and both are advanced
-    one step; the input is the 3x3 field patch of the coarse state after its
-    step and the target the one-step error of its spatial stress,
-    T^ij_fine(t+1) - T^ij_coarse(t+1), at the patch centre."""
-    import torch
-    X, T = [], []
-    snap = set(int(round(steps * k / snapshots)) for k in range(snapshots))
-    ident = rlbm.MLP(max_batch=side * side, n_hidden=1, hidden=8)   # feature kernel with unit scales
-    ident.set_norm(np.zeros(7), np.ones(7), np.zeros(3), np.ones(3))
-    for sd in seeds:
-        Kn, fld, tau, dt = shock(side, sd)
-        f = make_solver(K_fine, side, fld, tau, dt)
-        c = make_solver(K_coarse, side, fld, tau, dt)
-        for t in range(steps):
-            if t in snap:
-                rlbm.resample(f, c)
-                c.step(1)
-                f.step(1)
-                tgt = spatial_stress(rlbm.site_stats(f)) - spatial_stress(rlbm.site_stats(c))
-                raw = ident.features(c)[:, :63]
-                idx = W.uniform(seed_rows * 7919 + sd * 131 + t, np.arange(rows_per_snapshot))
-                sel = torch.as_tensor((idx * side * side).astype(np.int64), device="cuda")
-                X.append(raw[sel].cpu().numpy())
-                T.append(tgt[sel].cpu().numpy())
-            else:
-                f.step(1)
-        del f, c
-    return np.concatenate(X), np.concatenate(T)
-
-
 def collect(side, seeds, K_coarse, K_fine, steps, snapshots, rows_per_snapshot, net=None, seed_rows=0, log=None):
     """Training rows, teacher-forced.  A fine and a coarse run start from the
     same state and step in lockstep; after every coarse step its shear stress
@@ -148,6 +116,35 @@ def collect(side, seeds, K_coarse, K_fine, steps, snapshots, rows_per_snapshot, 
     return np.concatenate(X), np.concatenate(T)
 
 
+def collect_readout(side, seeds, K_coarse, K_fine, steps, rows, log=None):
+    """Training rows of the readout correction.  Per seed a fine and a coarse
+    run go to the end; the input is the coarse run's 3x3 field patch at the
+    end with log10 Kn in column 63, the target the fine-minus-coarse fields
+    at the patch centre: relative for n and eps, absolute for U^x, U^y."""
+    X, T = [], []
+    ident = rlbm.MLP(max_batch=side * side, n_hidden=1, hidden=8)   # feature kernel with unit scales
+    ident.set_norm(np.zeros(7), np.ones(7), np.zeros(3), np.ones(3))
+    for si, sd in enumerate(seeds):
+        if log and si % 20 == 0:
+            log("learned: collecting seed %d of %d" % (si, len(seeds)))
+        Kn, fld, tau, dt = shock(side, sd)
+        f = make_solver(K_fine, side, fld, tau, dt)
+        f.step(steps)
+        F = run_fields(f)
+        del f
+        c = make_solver(K_coarse, side, fld, tau, dt)
+        c.step(steps)
+        C = run_fields(c)
+        raw = ident.features(c)[:, :63].cpu().numpy()
+        del c
+        tgt = np.stack([(F["n"] - C["n"]) / C["n"], (F["eps"] - C["eps"]) / C["eps"], F["ux"] - C["ux"],
+                        F["uy"] - C["uy"]], axis=-1).reshape(-1, 4)
+        idx = (W.uniform(sd * 17 + 5, np.arange(rows)) * side * side).astype(np.int64)
+        X.append(np.concatenate([raw[idx], np.full((rows, 1), np.log10(Kn))], axis=1))
+        T.append(tgt[idx])
+    return np.concatenate(X), np.concatenate(T)
+
+
 class Normaliser:
     def __init__(self, X, T):
         centre = X[:, 28:35]   # neighbour 4 = the site itself
@@ -157,8 +154,11 @@ class Normaliser:
         self.out_sig = T.std(axis=0) + 1e-9
 
     def inputs(self, X):
-        Xn = (X.reshape(-1, 9, 7) - self.in_mu) / self.in_sig
-        return np.concatenate([Xn.reshape(-1, 63), np.zeros((X.shape[0], 1))], axis=1).astype(np.float32)
+        """Normalised patches; column 63 carried over from X when it has one
+        (the readout's per-run input), else zero."""
+        Xn = (X[:, :63].reshape(-1, 9, 7) - self.in_mu) / self.in_sig
+        extra = X[:, 63:64] if X.shape[1] == 64 else np.zeros((X.shape[0], 1))
+        return np.concatenate([Xn.reshape(-1, 63), extra], axis=1).astype(np.float32)
 
     def targets(self, T):
         return ((T - self.out_mu) / self.out_sig).astype(np.float32)
@@ -226,6 +226,31 @@ def evaluate(net, side, seeds, K_coarse, K_fine, steps, scale=1.0, relax=False):
     return res
 
 
+def evaluate_readout(net, side, seeds, K_coarse, K_fine, steps):
+    """Per-seed errors of the plain coarse run and of its readout-corrected
+    fields against the plain fine run, and the wall time of the coarse run
+    with its readout."""
+    import torch
+    res = []
+    for sd in seeds:
+        Kn, fld, tau, dt = shock(side, sd)
+        f = make_solver(K_fine, side, fld, tau, dt)
+        f.step(steps)
+        ref = run_fields(f)
+        del f
+        c = make_solver(K_coarse, side, fld, tau, dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.step(steps)
+        n, eps, ux, uy = net.readout(c, float(np.log10(Kn)))
+        tc = time.perf_counter() - t0
+        plain = rel_errors(run_fields(c), ref)
+        corr = rel_errors(dict(n=n, eps=eps, ux=ux, uy=uy), ref)
+        del c
+        res.append(dict(seed=sd, Kn=Kn, plain=plain, corrected=corr, t_corrected=tc))
+    return res
+
+
 def sweep_plain(side, seeds, Ks, K_fine, steps):
     """Mean error of the plain solver per angle count against K_fine, and its
     time per run."""
@@ -278,22 +303,28 @@ def time_at_K(sweep, K):
 
 def study(side=512, K_coarse=24, K_fine=384, steps=230, train_seeds=range(200), eval_seeds=range(10000, 10020),
           Ks=(24, 32, 48, 64, 96, 128, 192, 256, 384), snapshots=10, rows=4096, epochs=10, batch=4096, lr=1e-3,
-          dagger=0, log=None):
-    """The learned form end to end: teacher-forced data, training, in-loop
-    use on held-out seeds, the plain sweep over K and the equal-error
-    comparison.  Returns a dict of errors, K* and speedups per field."""
+          dagger=0, mode="readout", log=None):
+    """The learned form end to end: data, training, use on held-out seeds,
+    the plain sweep over K and the equal-error comparison.  mode "readout":
+    the network corrects the coarse run's fields at the end (rows of
+    collect_readout, 4 outputs); mode "step": it corrects the shear stress
+    after every step (teacher-forced rows of collect, 3 outputs).  Returns a
+    dict of errors, K* and speedups per field."""
     import torch
     say = log or (lambda m: None)
     t0 = time.perf_counter()
-    X, T = collect(side, list(train_seeds), K_coarse, K_fine, steps, snapshots, rows, log=say)
+    if mode == "readout":
+        X, T = collect_readout(side, list(train_seeds), K_coarse, K_fine, steps, rows * snapshots, log=say)
+    else:
+        X, T = collect(side, list(train_seeds), K_coarse, K_fine, steps, snapshots, rows, log=say)
     say("learned: %d training rows in %.1f s" % (X.shape[0], time.perf_counter() - t0))
     nm = Normaliser(X, T)
-    net = rlbm.MLP(max_batch=side * side)
+    net = rlbm.MLP(max_batch=side * side, out_dim=T.shape[1])
     net.init_params(seed=1)
     nm.apply(net)
     t1 = time.perf_counter()
     losses = train(net, nm.inputs(X), nm.targets(T), epochs=epochs, batch=batch, lr=lr, log=say)
-    for r in range(dagger):
+    for r in range(dagger if mode == "step" else 0):
         seeds = [100000 + 1000 * r + k for k in range(len(list(train_seeds)) // 4)]
         X2, T2 = collect(side, seeds, K_coarse, K_fine, steps, snapshots, rows, net=net, seed_rows=r + 1)
         X, T = np.concatenate([X, X2]), np.concatenate([T, T2])
@@ -301,13 +332,17 @@ def study(side=512, K_coarse=24, K_fine=384, steps=230, train_seeds=range(200), 
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     say("learned: trained, loss %.4g -> %.4g in %.1f s" % (losses[0], losses[-1], t_train))
-    res = evaluate(net, side, list(eval_seeds), K_coarse, K_fine, steps)
+    if mode == "readout":
+        res = evaluate_readout(net, side, list(eval_seeds), K_coarse, K_fine, steps)
+    else:
+        res = evaluate(net, side, list(eval_seeds), K_coarse, K_fine, steps)
     corr = {k: float(np.mean([r["corrected"][k] for r in res])) for k in ("n", "eps", "beta")}
     plain = {k: float(np.mean([r["plain"][k] for r in res])) for k in ("n", "eps", "beta")}
     t_corr = float(np.mean([r["t_corrected"] for r in res]))
     say("learned: coarse %s corrected %s" % (plain, corr))
     sw = sweep_plain(side, list(eval_seeds), Ks, K_fine, steps)
-    out = dict(plain_coarse_err=plain, corrected_err=corr, wall_corrected_s=t_corr,
+    out = dict(mode=mode, plain_coarse_err=plain, corrected_err=corr, wall_corrected_s=t_corr,
+               per_seed=[dict(seed=r["seed"], Kn=r["Kn"], plain=r["plain"], corrected=r["corrected"]) for r in res],
                sweep={int(K): v for K, v in sw.items()}, train_rows=int(X.shape[0]), train_loss=[losses[0], losses[-1]],
                train_s=t_train, K_star={}, speedup={})
     for f in ("n", "eps", "beta"):

@@ -70,6 +70,7 @@ SIGNATURES = [
     ("rlbm_site_stats", ctypes.c_int, [_vp, _vp]),
     ("rlbm_mlp_features", ctypes.c_int, [_vp, _vp, _vp]),
     ("rlbm_mlp_correct", ctypes.c_int, [_vp, _vp, ctypes.c_float, ctypes.c_int]),
+    ("rlbm_mlp_readout", ctypes.c_int, [_vp, _vp, ctypes.c_float, _dp, _dp, _dp, _dp]),
     ("rlbm_add_stress", ctypes.c_int, [_vp, _vp, ctypes.c_float]),
     ("rlbm_resample", ctypes.c_int, [_vp, _vp]),
     ("rlbm_mlp_last_error", ctypes.c_char_p, [_vp]),
@@ -516,6 +517,16 @@ class MLP:
         X = torch.empty((solver.nx * solver.ny, self.in_dim), dtype=torch.float32, device="cuda")
         self._check(lib().rlbm_mlp_features(solver._h, self._h, _fptr(X)))
         return X
+
+    def readout(self, solver, extra):
+        """Readout-corrected fields n, eps, U^x, U^y ([ny][nx] each) of the
+        solver's current populations (a network with out_dim = 4)."""
+        out = [np.empty((solver.ny, solver.nx)) for _ in range(4)]
+        rc = lib().rlbm_mlp_readout(solver._h, self._h, float(extra), *[_p(a) for a in out])
+        if rc == RLBM_ENONPHYS:
+            solver._check(rc)
+        self._check(rc)
+        return out
 
     def correct(self, solver, scale=1.0, relax=False):
         self._check(lib().rlbm_mlp_correct(solver._h, self._h, float(scale), int(bool(relax))))
