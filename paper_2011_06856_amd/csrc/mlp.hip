@@ -89,6 +89,11 @@ __global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ A, const
 // register r of lane l is C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
+// 1: inference through the layer-by-layer kernels instead of the one-pass one.
+#ifndef RLBM_MLP_LAYERED
+#define RLBM_MLP_LAYERED 0
+#endif
+
 template <bool TA, bool TB, typename TBt>
 __global__ __launch_bounds__(256) void k_gemm_mfma(const float* __restrict__ A, const TBt* __restrict__ B,
                                                    float* __restrict__ C, int M, int N, int K, int accumulate)
@@ -135,6 +140,86 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const float* __restrict__ A, 
 }
 
 __device__ inline float gelu(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
+
+// Inference in one pass: a work-group takes 64 rows through every layer of
+// a 64 -> 128^nh -> out network (out <= 32), the activations staying in LDS.
+// Per layer the work-group stages W^T in LDS (bfloat16), and wave w forms
+// output columns 32w..32w+31 of both 32-row blocks with
+// v_mfma_f32_32x32x2f32, k in the same order as k_gemm_mfma, then adds the
+// bias and applies GELU exactly as k_bias_act: the outputs equal those of
+// the layer-by-layer path bit for bit.  The last layer (one 32-column block,
+// padded with zero weights) is formed by waves 0 and 1.
+struct FusedNet {
+    int nl, out;          // layers (hidden + output), outputs
+    int woff[9], boff[9]; // offsets of W_l ([dout][din]) and b_l
+};
+
+__global__ __launch_bounds__(256) void k_mlp_fused(const float* __restrict__ X, const unsigned short* __restrict__ pbf,
+                                                   const float* __restrict__ p, float* __restrict__ Y, int B, FusedNet net)
+{
+    __shared__ float act[64 * 128];            // [row][col ^ (row & 31)]: conflict-free column reads
+    __shared__ unsigned short Ws[128 * 128];   // W^T of the current layer, [k][n]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const long r0 = (long)blockIdx.x * 64;
+    auto A = [&](int row, int col) -> float& { return act[row * 128 + (col ^ (row & 31))]; };
+    for (int e = tid; e < 64 * 64; e += 256) {
+        const int r = e >> 6, k = e & 63;
+        A(r, k) = r0 + r < B ? X[(r0 + r) * 64 + k] : 0.f;
+    }
+    for (int l = 0; l < net.nl; ++l) {
+        const bool last = l == net.nl - 1;
+        const int din = l == 0 ? 64 : 128, dout = last ? net.out : 128, ncols = last ? 32 : 128;
+        const unsigned short* W = pbf + net.woff[l];
+        // stage W^T: thread -> column n, 8 consecutive k per read
+        for (int e = tid; e < ncols * (din / 8); e += 256) {
+            const int n = e % ncols, kc = (e / ncols) * 8;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) Ws[(kc + j) * 128 + n] = n < dout ? W[(long)n * din + kc + j] : 0;
+        }
+        __syncthreads();
+        floatx16 acc0, acc1;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0.f;
+        const int cb = last ? 0 : w;
+        if (!last) {
+            for (int k0 = 0; k0 < din; k0 += 2) {
+                const int k = k0 + (lane >> 5);
+                const float b = bf2f(Ws[k * 128 + cb * 32 + (lane & 31)]);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A(lane & 31, k), b, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(A(32 + (lane & 31), k), b, acc1, 0, 0, 0);
+            }
+        } else if (w < 2) {
+            for (int k0 = 0; k0 < din; k0 += 2) {
+                const int k = k0 + (lane >> 5);
+                const float b = bf2f(Ws[k * 128 + (lane & 31)]);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A(w * 32 + (lane & 31), k), b, acc0, 0, 0, 0);
+            }
+        }
+        __syncthreads();   // every read of this layer's inputs and weights is done
+        const float* bias = p + net.boff[l];
+        if (!last) {
+            const int col = cb * 32 + (lane & 31);
+            const float bc = bias[col];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                A(row, col) = gelu(acc0[r] + bc);
+                A(32 + row, col) = gelu(acc1[r] + bc);
+            }
+            __syncthreads();
+        } else if (w < 2) {
+            const int col = lane & 31;
+            if (col < dout) {
+                const float bc = bias[col];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const long row = r0 + w * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    if (row < B) Y[row * dout + col] = acc0[r] + bc;
+                }
+            }
+        }
+    }
+}
 __device__ inline float gelu_d(float x)
 {
     return 0.5f * (1.f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * __expf(-0.5f * x * x);
@@ -393,6 +478,12 @@ hipError_t gemm(hipStream_t st, const float* A, const TBt* B, float* C, int M, i
 }
 
 // Forward for B rows of X; keeps Z and A of the hidden layers for backward.
+// Inference: the one-pass kernel where the shape allows it (input 64,
+// hidden 128, at most 32 outputs); it gives the same outputs as the
+// layer-by-layer path, which training uses (it keeps every layer's
+// pre-activations for the backward pass).
+hipError_t infer(rlbm_mlp m, const float* X, int B, float* Y);
+
 hipError_t forward(rlbm_mlp m, const float* X, int B, float* Y)
 {
     const int L = m->nh + 1;
@@ -410,6 +501,20 @@ hipError_t forward(rlbm_mlp m, const float* X, int B, float* Y)
         in = Aout;
     }
     return hipSuccess;
+}
+
+hipError_t infer(rlbm_mlp m, const float* X, int B, float* Y)
+{
+    if (m->in != 64 || m->hid != 128 || m->out > 32 || m->nh + 1 > 9 || RLBM_MLP_LAYERED) return forward(m, X, B, Y);
+    FusedNet net;
+    net.nl = m->nh + 1;
+    net.out = m->out;
+    for (int l = 0; l < net.nl; ++l) {
+        net.woff[l] = (int)m->woff[l];
+        net.boff[l] = (int)m->boff[l];
+    }
+    hipLaunchKernelGGL(k_mlp_fused, dim3((unsigned)((B + 63) / 64)), dim3(256), 0, m->st, X, m->pbf, m->p, Y, B, net);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -553,7 +658,7 @@ int rlbm_mlp_set_norm(rlbm_mlp m, const float* in_mu, const float* in_sig, const
 int rlbm_mlp_forward(rlbm_mlp m, const float* dX, int B, float* dY)
 {
     if (!m || !dX || !dY || B < 1 || B > m->maxb) return RLBM_EINVAL;
-    hipError_t e = forward(m, dX, B, dY);
+    hipError_t e = infer(m, dX, B, dY);
     return e == hipSuccess ? RLBM_OK : mfail(m, RLBM_EDEVICE, hipGetErrorString(e));
 }
 

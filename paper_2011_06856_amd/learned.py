@@ -215,11 +215,12 @@ def evaluate(net, side, seeds, K_coarse, K_fine, steps, scale=1.0, relax=False):
         for t in range(steps):
             c.step(1)
             net.correct(c, scale, relax=relax)
-        torch.cuda.synchronize()
-        tc = time.perf_counter() - t0
         try:
-            corr = rel_errors(run_fields(c), ref)
+            fields = run_fields(c)
+            tc = time.perf_counter() - t0
+            corr = rel_errors(fields, ref)
         except rlbm.NonPhysicalState:
+            tc = time.perf_counter() - t0
             corr = {k: float("inf") for k in plain}
         del c
         res.append(dict(seed=sd, Kn=Kn, plain=plain, corrected=corr, t_fine=tf, t_corrected=tc))
@@ -253,7 +254,7 @@ def evaluate_readout(net, side, seeds, K_coarse, K_fine, steps):
 
 def sweep_plain(side, seeds, Ks, K_fine, steps):
     """Mean error of the plain solver per angle count against K_fine, and its
-    time per run."""
+    time per run (steps and the read-out of its fields)."""
     import torch
     out = {}
     refs = {}
@@ -271,9 +272,9 @@ def sweep_plain(side, seeds, Ks, K_fine, steps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             s.step(steps)
-            torch.cuda.synchronize()
+            fields = run_fields(s)   # the run's output, read out as the corrected runs' are
             times.append(time.perf_counter() - t0)
-            errs.append(rel_errors(run_fields(s), refs[sd]))
+            errs.append(rel_errors(fields, refs[sd]))
             del s
         out[K] = dict(err={k: float(np.mean([e[k] for e in errs])) for k in errs[0]}, time=float(np.mean(times)))
     return out
