@@ -218,7 +218,7 @@ def main():
     ap.add_argument("--form", default="plain", choices=["plain", "batched", "learned", "precision"])
     ap.add_argument("--train-seeds", type=int, default=200, help="learned form: training seeds")
     ap.add_argument("--eval-seeds", type=int, default=20, help="learned form: held-out seeds")
-    ap.add_argument("--epochs", type=int, default=10, help="learned form: training epochs")
+    ap.add_argument("--epochs", type=int, default=15, help="learned form: training epochs")
     ap.add_argument("--learned-mode", default="readout", choices=["readout", "step"],
                     help="learned form: correct the fields at readout, or the shear stress after every step")
     ap.add_argument("--tune-cache", action="store_true", help="reuse/store the autotuner choice in _tune_cache.json")
