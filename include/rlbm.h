@@ -286,8 +286,12 @@ int rlbm_mlp_adam_step(rlbm_mlp m, float lr, float beta1, float beta2, float eps
  * pi^ij = T^ij - (eps + P) U^i U^j - P delta^ij, P = eps/2 (Eq. ll-decomp). */
 int rlbm_site_stats(rlbm_ctx c, float* dstats);
 /* Network inputs of every site: the 7 fields of its 3x3 neighbourhood
- * (periodic), normalised, device [S][64] (column 63 zero). */
+ * (periodic), normalised, device [S][64]; column 63 holds the network's
+ * per-run input (rlbm_mlp_set_extra, 0 by default). */
 int rlbm_mlp_features(rlbm_ctx c, rlbm_mlp m, float* dX);
+/* The per-run input of the features' column 63 (e.g. log10 Kn), used by
+ * rlbm_mlp_features and rlbm_mlp_correct until changed. */
+int rlbm_mlp_set_extra(rlbm_mlp m, float extra);
 /*
  * In-loop correction: inputs, forward pass, and the predicted change
  * (dT^xx, dT^xy, dT^yy), times scale, put into the populations through the
@@ -306,7 +310,8 @@ int rlbm_mlp_correct(rlbm_ctx c, rlbm_mlp m, float scale, int relax);
  * network with out_dim = 4; the correction is to the fields of Eq. rel_err,
  * not to the populations):
  *   inputs   the features of rlbm_mlp_features with column 63 = extra (the
- *            network is trained with a per-run scalar there, log10 Kn);
+ *            network is trained with a per-run scalar there, log10 Kn; it
+ *            also becomes the network's rlbm_mlp_set_extra value);
  *   outputs  y (de-normalised with rlbm_mlp_set_norm's out_mu, out_sig);
  *   fields   n (1 + y0), eps (1 + y1), U^x + y2, U^y + y3 of the current
  *            populations, to host arrays [ny][nx] (caller-owned, any NULL).

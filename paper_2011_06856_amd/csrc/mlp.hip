@@ -340,7 +340,7 @@ __global__ __launch_bounds__(256) void k_site_stats(const TS* __restrict__ f, co
 // neighbour j = (dy+1)*3 + (dx+1), field k at column 7j + k, normalised by
 // (x - mu_k) / sigma_k; column 63 is zero.
 __global__ void k_patch(const float* __restrict__ stats, float* __restrict__ X, int nx, int ny,
-                        const float* __restrict__ mu, const float* __restrict__ sig)
+                        const float* __restrict__ mu, const float* __restrict__ sig, float extra)
 {
     const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= (long)nx * ny) return;
@@ -353,15 +353,7 @@ __global__ void k_patch(const float* __restrict__ stats, float* __restrict__ X, 
             const int j = (dy + 1) * 3 + (dx + 1);
             for (int k = 0; k < 7; ++k) o[7 * j + k] = (st[k] - mu[k]) / sig[k];
         }
-    o[63] = 0.f;
-}
-
-// Column 63 of the features: a per-run input (the readout network takes
-// log10 Kn there).
-__global__ void k_set_col63(float* __restrict__ X, long S, float v)
-{
-    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < S) X[s * 64 + 63] = v;
+    o[63] = extra;
 }
 
 // Readout correction of the FP64 fields f = [n | eps | U^x | U^y] (each S):
@@ -453,6 +445,7 @@ struct rlbm_mlp_s {
     float* stats = nullptr;
     double* partial = nullptr;
     float* norm = nullptr;   // in_mu[7], in_sig[7], out_mu[out], out_sig[out] (out <= 8)
+    float extra = 0.f;       // input column 63 (a per-run input, e.g. log10 Kn)
     int adam_t = 0;
     std::string err;
 };
@@ -740,7 +733,7 @@ int rlbm_mlp_features(rlbm_ctx c, rlbm_mlp m, float* dX)
     int rc = rlbm_site_stats(c, m->stats);
     if (rc != RLBM_OK) return rc;
     hipLaunchKernelGGL(k_patch, dim3(nblk(c->S)), dim3(256), 0, c->st, m->stats, dX, c->nx, c->ny, m->norm,
-                       m->norm + 7);
+                       m->norm + 7, m->extra);
     return hipGetLastError() == hipSuccess ? RLBM_OK : RLBM_EDEVICE;
 }
 
@@ -761,13 +754,20 @@ int rlbm_mlp_correct(rlbm_ctx c, rlbm_mlp m, float scale, int relax)
 // Readout correction of a context's fields: features with column 63 =
 // `extra`, forward pass, the fields of the current populations corrected by
 // the de-normalised outputs (k_readout), copied to the host.
+int rlbm_mlp_set_extra(rlbm_mlp m, float extra)
+{
+    if (!m) return RLBM_EINVAL;
+    m->extra = extra;
+    return RLBM_OK;
+}
+
 int rlbm_mlp_readout(rlbm_ctx c, rlbm_mlp m, float extra, double* n, double* eps, double* ux, double* uy)
 {
     if (!c || !m || !c->have_fields) return RLBM_EINVAL;
     if (m->out != 4) return mfail(m, RLBM_EINVAL, "the readout correction needs four outputs");
+    m->extra = extra;
     int rc = rlbm_mlp_features(c, m, m->X);
     if (rc != RLBM_OK) return rc;
-    hipLaunchKernelGGL(k_set_col63, dim3(nblk(c->S)), dim3(256), 0, c->st, m->X, (long)c->S, extra);
     if ((rc = rlbm_mlp_forward(m, m->X, (int)c->S, m->Y)) != RLBM_OK) return rc;
     hipError_t e = launch_fields(c->prec, c->f[c->cur], c->d_veld, c->d_fields, c->d_partials, c->d_flag, c->nx, c->ny,
                                  c->q.nvel, c->st);
@@ -830,7 +830,7 @@ int rlbm_resample(rlbm_ctx src, rlbm_ctx dst)
             hipLaunchKernelGGL((k_resample<float, float>), grid, dim3(256), 0, dst->st, (const float*)fs, (float*)fd, dR, src->S, Ks, Kd);
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(dst->st) != hipSuccess) rc = RLBM_EDEVICE;
     }
-    hipFree(dR);
+    (void)hipFree(dR);
     return rc;
 }
 

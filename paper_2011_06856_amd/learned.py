@@ -83,8 +83,8 @@ def collect(side, seeds, K_coarse, K_fine, steps, snapshots, rows_per_snapshot, 
     is set to the fine run's (the exact correction, added through the m = 2
     basis), so the coarse states are those of a perfectly corrected run.  At
     snapshot steps the input is the coarse run's 3x3 field patch before the
-    correction and the target the correction itself, pi_fine - pi_coarse, at
-    the patch centre.  With `net`, the network's own correction is applied
+    correction (with log10 Kn in column 63) and the target the correction
+    itself, pi_fine - pi_coarse, at the patch centre.  With `net`, the network's own correction is applied
     instead of the exact one, so that the rows come from the states it meets
     in use (targets stay the exact gaps)."""
     import torch
@@ -98,6 +98,8 @@ def collect(side, seeds, K_coarse, K_fine, steps, snapshots, rows_per_snapshot, 
         Kn, fld, tau, dt = shock(side, sd)
         f = make_solver(K_fine, side, fld, tau, dt)
         c = make_solver(K_coarse, side, fld, tau, dt)
+        if net is not None:
+            net.set_extra(np.log10(Kn))
         for t in range(1, steps + 1):
             f.step(1)
             c.step(1)
@@ -106,7 +108,8 @@ def collect(side, seeds, K_coarse, K_fine, steps, snapshots, rows_per_snapshot, 
                 raw = ident.features(c)[:, :63]
                 idx = W.uniform(seed_rows * 7919 + sd * 131 + t, np.arange(rows_per_snapshot))
                 sel = torch.as_tensor((idx * side * side).astype(np.int64), device="cuda")
-                X.append(raw[sel].cpu().numpy())
+                X.append(np.concatenate([raw[sel].cpu().numpy(), np.full((rows_per_snapshot, 1), np.log10(Kn))],
+                                        axis=1))
                 T.append(gap[sel].cpu().numpy())
             if net is None:
                 rlbm.add_stress(c, gap)
@@ -210,6 +213,7 @@ def evaluate(net, side, seeds, K_coarse, K_fine, steps, scale=1.0, relax=False):
         plain = rel_errors(run_fields(c), ref)
         del c
         c = make_solver(K_coarse, side, fld, tau, dt)
+        net.set_extra(np.log10(Kn))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for t in range(steps):

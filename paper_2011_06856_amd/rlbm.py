@@ -71,6 +71,7 @@ SIGNATURES = [
     ("rlbm_mlp_features", ctypes.c_int, [_vp, _vp, _vp]),
     ("rlbm_mlp_correct", ctypes.c_int, [_vp, _vp, ctypes.c_float, ctypes.c_int]),
     ("rlbm_mlp_readout", ctypes.c_int, [_vp, _vp, ctypes.c_float, _dp, _dp, _dp, _dp]),
+    ("rlbm_mlp_set_extra", ctypes.c_int, [_vp, ctypes.c_float]),
     ("rlbm_add_stress", ctypes.c_int, [_vp, _vp, ctypes.c_float]),
     ("rlbm_resample", ctypes.c_int, [_vp, _vp]),
     ("rlbm_mlp_last_error", ctypes.c_char_p, [_vp]),
@@ -517,6 +518,10 @@ class MLP:
         X = torch.empty((solver.nx * solver.ny, self.in_dim), dtype=torch.float32, device="cuda")
         self._check(lib().rlbm_mlp_features(solver._h, self._h, _fptr(X)))
         return X
+
+    def set_extra(self, extra):
+        """The per-run input in column 63 of the features (e.g. log10 Kn)."""
+        self._check(lib().rlbm_mlp_set_extra(self._h, float(extra)))
 
     def readout(self, solver, extra):
         """Readout-corrected fields n, eps, U^x, U^y ([ny][nx] each) of the
