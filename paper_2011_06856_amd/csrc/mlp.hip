@@ -751,9 +751,7 @@ int rlbm_mlp_correct(rlbm_ctx c, rlbm_mlp m, float scale, int relax)
     return add_stress(c, m->Y, m->norm + 14, m->norm + 17, relax ? m->stats : nullptr, scale);
 }
 
-// Readout correction of a context's fields: features with column 63 =
-// `extra`, forward pass, the fields of the current populations corrected by
-// the de-normalised outputs (k_readout), copied to the host.
+// The per-run input that the features carry in column 63.
 int rlbm_mlp_set_extra(rlbm_mlp m, float extra)
 {
     if (!m) return RLBM_EINVAL;
@@ -761,6 +759,9 @@ int rlbm_mlp_set_extra(rlbm_mlp m, float extra)
     return RLBM_OK;
 }
 
+// Readout correction of a context's fields: features with column 63 =
+// `extra`, forward pass, the fields of the current populations corrected by
+// the de-normalised outputs (k_readout), copied to the host.
 int rlbm_mlp_readout(rlbm_ctx c, rlbm_mlp m, float extra, double* n, double* eps, double* ux, double* uy)
 {
     if (!c || !m || !c->have_fields) return RLBM_EINVAL;
