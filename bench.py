@@ -192,7 +192,8 @@ def learned_form(a):
     from paper_2011_06856_amd import learned as Lr
     say = lambda m: print("bench: " + m, file=sys.stderr, flush=True)
     r = Lr.study(side=a.side, steps=a.steps, train_seeds=range(a.train_seeds),
-                 eval_seeds=range(10000, 10000 + a.eval_seeds), epochs=a.epochs, mode=a.learned_mode, log=say)
+                 eval_seeds=range(10000, 10000 + a.eval_seeds), epochs=a.epochs, mode=a.learned_mode,
+                 rows=a.rows, log=say)
     sp = [v for v in r["speedup"].values() if v]
     return {
         "metric": METRIC, "value": min(sp) if len(sp) == 3 else None, "unit": "x (wall plain K* / wall coarse+MLP)",
@@ -200,7 +201,7 @@ def learned_form(a):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "learned_shocks_%d_np4_k24_vs_k384" % a.side, "train_seeds": a.train_seeds,
                    "eval_seeds": a.eval_seeds, "steps_per_run": a.steps, "epochs": a.epochs,
-                   "correction": a.learned_mode},
+                   "correction": a.learned_mode, "rows": a.rows},
         "learned": r,
     }
 
@@ -219,6 +220,9 @@ def main():
     ap.add_argument("--train-seeds", type=int, default=200, help="learned form: training seeds")
     ap.add_argument("--eval-seeds", type=int, default=20, help="learned form: held-out seeds")
     ap.add_argument("--epochs", type=int, default=15, help="learned form: training epochs")
+    ap.add_argument("--rows", type=int, default=4096,
+                    help="learned form: sampled sites per snapshot (10 snapshots a seed in the step mode; "
+                         "the readout takes 10x this many sites of each run's end state)")
     ap.add_argument("--learned-mode", default="readout", choices=["readout", "step"],
                     help="learned form: correct the fields at readout, or the shear stress after every step")
     ap.add_argument("--tune-cache", action="store_true", help="reuse/store the autotuner choice in _tune_cache.json")
