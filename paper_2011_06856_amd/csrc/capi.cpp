@@ -45,11 +45,12 @@ void free_tables(rlbm_ctx c)
 {
     if (c->d_srec) (void)hipFree(c->d_srec);
     if (c->d_crec) (void)hipFree(c->d_crec);
+    if (c->d_sgn) (void)hipFree(c->d_sgn);
     if (c->d_veld) (void)hipFree(c->d_veld);
     if (c->d_G) (void)hipFree(c->d_G);
     if (c->d_Pc) (void)hipFree(c->d_Pc);
     if (c->d_corr) (void)hipFree(c->d_corr);
-    c->d_srec = nullptr; c->d_crec = nullptr; c->d_veld = nullptr; c->d_corr = nullptr; c->d_G = nullptr; c->d_Pc = nullptr;
+    c->d_srec = nullptr; c->d_crec = nullptr; c->d_sgn = nullptr; c->d_veld = nullptr; c->d_corr = nullptr; c->d_G = nullptr; c->d_Pc = nullptr;
 }
 
 template <typename T, int NM>
@@ -58,6 +59,7 @@ int upload_tables_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, long long
     const size_t nv = c->q.nvel, npad = nv + RLBM_VPAD;
     std::vector<SRec<T>> sr(npad);
     std::vector<CRec<T, NM>> cr(npad);
+    std::vector<unsigned char> sg(npad, 0);
     for (size_t v = 0; v < npad; ++v) {
         const bool real = v < nv;
         SRec<T>& A = sr[v];
@@ -71,6 +73,7 @@ int upload_tables_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, long long
         for (int j = 0; j < (int)(sizeof(A.P) / sizeof(T)); ++j) A.P[j] = (T)R.P[j];
         for (int t = 0; t < 2 * NM + 1; ++t) B.H[t] = (T)R.H[t];
         B.cth = (T)R.cth; B.sth = (T)R.sth;
+        sg[v] = (unsigned char)((R.sx > 0 ? 0 : 1) | (R.sy > 0 ? 0 : 2));
     }
     hipError_t e;
     if ((e = hipMalloc(&c->d_srec, npad * sizeof(SRec<T>))) != hipSuccess) return fail(c, RLBM_ENOMEM, "table alloc");
@@ -78,6 +81,9 @@ int upload_tables_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, long long
     if ((e = hipMemcpy(c->d_srec, sr.data(), npad * sizeof(SRec<T>), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(c, e, "table upload");
     if ((e = hipMemcpy(c->d_crec, cr.data(), npad * sizeof(CRec<T, NM>), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(c, e, "table upload");
+    if ((e = hipMalloc((void**)&c->d_sgn, npad)) != hipSuccess) return fail(c, RLBM_ENOMEM, "table alloc");
+    if ((e = hipMemcpy(c->d_sgn, sg.data(), npad, hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(c, e, "table upload");
     return RLBM_OK;
 }
@@ -121,6 +127,7 @@ SCParams make_params(rlbm_ctx c, int waves)
     p.fin = p.fout = nullptr;
     p.srec = c->d_srec;
     p.crec = c->d_crec;
+    p.sgn = c->d_sgn;
     p.G = c->d_G;
     p.Pc = c->d_Pc;
     p.nx = c->nx; p.ny = c->ny; p.nvel = c->q.nvel; p.K = c->q.K; p.Np = c->q.Np; p.N = c->q.N;

@@ -90,6 +90,7 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
     CDbl* const Gtab = (CDbl*)Gtab_;
     CDbl* const Pc = (CDbl*)Pc_;
     static_assert(VPT % LB == 0, "VPT must be a multiple of the load batch");
+    static_assert(LB <= 8 && LB % 4 == 0, "a batch's upwind signs are read as one 8-byte word");
     const int NW = blockDim.x >> 6;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -140,10 +141,10 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
     };
 
     auto ld = [](const char* base, unsigned off) __attribute__((always_inline)) -> TC { return (TC)*reinterpret_cast<const TS*>(base + off); };
-    auto load4 = [&](auto fast, int v, const char* p0, TC* r) __attribute__((always_inline)) {
-        CSRec& M = srec[v];
-        const bool cneg = xneg(M.P[1]);   // upwind column x + 1
-        const char* p1 = p0 + (xneg(M.P[2]) ? dpb : dmb);
+    // code: bit 0 upwind column x + 1, bit 1 upwind row y + 1
+    auto load4 = [&](auto fast, unsigned code, const char* p0, TC* r) __attribute__((always_inline)) {
+        const bool cneg = code & 1;
+        const char* p1 = p0 + ((code & 2) ? dpb : dmb);
         if (decltype(fast)::value) {
             const int dx = cneg ? (int)ES : -(int)ES;
             r[0] = ld(p0, ocb); r[1] = ld(p0 + dx, ocb); r[2] = ld(p1, ocb); r[3] = ld(p1 + dx, ocb);
@@ -167,8 +168,13 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
         for (int kb = 0; kb < VPT / LB; ++kb) {
             if (kb < nbatch) {
                 TC raw[LB][4];
+                // the batch's upwind signs in one scalar load (the streaming
+                // records are needed only for the arithmetic that follows)
+                const unsigned long long sg =
+                    *(const RLBM_CONST_AS unsigned long long*)((const RLBM_CONST_AS unsigned char*)P.sgn + v0 + kb * LB);
 #pragma unroll
-                for (int b = 0; b < LB; ++b) load4(fast, v0 + kb * LB + b, rnext(v0 + kb * LB + b), raw[b]);
+                for (int b = 0; b < LB; ++b)
+                    load4(fast, (unsigned)(sg >> (8 * b)) & 3u, rnext(v0 + kb * LB + b), raw[b]);
 #pragma unroll
                 for (int b = 0; b < LB; ++b) {
                     const int v = v0 + kb * LB + b;
@@ -182,7 +188,7 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
         }
         for (int v = v0 + VPT; v < v0 + P.chunk; ++v) {
             TC r[4];
-            load4(fast, v, inb + rplane(v), r);
+            load4(fast, (xneg(srec[v].P[1]) ? 1u : 0u) | (xneg(srec[v].P[2]) ? 2u : 0u), inb + rplane(v), r);
             const TC f = bilin(v, r);
             CSRec& R = srec[v];
 #pragma unroll
@@ -279,7 +285,7 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
         }
         for (int v = v0 + VPT; v < v0 + P.chunk; ++v) {
             TC r[4];
-            load4(fast, v, inb + rplane(v), r);
+            load4(fast, (xneg(srec[v].P[1]) ? 1u : 0u) | (xneg(srec[v].P[2]) ? 2u : 0u), inb + rplane(v), r);
             collide(fast, v, outb + wplane(v), bilin(v, r));
         }
     };

@@ -189,6 +189,7 @@ struct SCParams {
     void* fout;
     const void* srec;      // SRec<TC>[nvel + RLBM_VPAD]
     const void* crec;      // CRec<TC, NM>[nvel + RLBM_VPAD]
+    const unsigned char* sgn;   // [nvel + RLBM_VPAD]: bit 0 cos < 0, bit 1 sin < 0 (upwind x + 1, y + 1)
     const double* G;       // [Np][NMAX+1][NMAX+1]
     const double* Pc;
     int nx, ny, nvel, K, Np, N;
@@ -238,6 +239,7 @@ struct rlbm_ctx_s {
     int* d_flag = nullptr;
     void* d_srec = nullptr;              // SRec<TC>[nvel + RLBM_VPAD]
     void* d_crec = nullptr;              // CRec<TC, NM>[nvel + RLBM_VPAD]
+    unsigned char* d_sgn = nullptr;      // upwind signs per table entry [nvel + RLBM_VPAD]
     VelRec<double>* d_veld = nullptr;    // FP64 table for init and fields [nvel]
     double* d_G = nullptr;
     double* d_Pc = nullptr;
