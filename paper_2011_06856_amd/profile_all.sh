@@ -28,3 +28,36 @@ run() {   # name, kernel, launch bytes, stats args, counter args
 run stream_collide_f32_circular_1024 "k_stream_collide<float, float, 3, 64>" 2147483648 "--steps 200" "--steps 4"
 run push_step_f32_quadrant_2048 "k_push_step<float, 5, 8, false>" 51539607552 \
     "--workload quadrant --side 2048 --steps 20" "--workload quadrant --side 2048 --steps 3"
+
+# The memory ceiling of the tile kernel's access pattern without its
+# arithmetic (probes/access_pattern.hip): its own event timing and the
+# rocprofv3 kernel statistics, in OUT/access_pattern_1024.md.
+D=$OUT/raw/access_pattern
+mkdir -p $D
+/opt/rocm/bin/hipcc -O3 --offload-arch=gfx950 -Xclang -target-feature -Xclang -packed-fp32-ops \
+    $ROOT/paper_2011_06856_amd/probes/access_pattern.hip -o $D/access_pattern
+timeout -s KILL 180 rocprofv3 --kernel-trace --stats -d $D/stats -o run --output-format csv -- $D/access_pattern > $D/out.txt
+{
+    echo "# access_pattern_1024"
+    echo
+    echo "Command (run from the repository root on a machine with the GPU):"
+    echo
+    echo '```'
+    echo "hipcc -O3 --offload-arch=gfx950 -Xclang -target-feature -Xclang -packed-fp32-ops paper_2011_06856_amd/probes/access_pattern.hip -o access_pattern"
+    echo "rocprofv3 --kernel-trace --stats -- ./access_pattern   (bash paper_2011_06856_amd/profile_all.sh)"
+    echo '```'
+    echo
+    echo "f[v][y][x], FP32, 1024^2 sites x 256 planes (1.07 GB per buffer); GB/s counts 2 x 1.07 GB per launch."
+    echo
+    echo "## Event timing (the program's output)"
+    echo
+    echo '```'
+    cat $D/out.txt
+    echo '```'
+    echo
+    echo "## rocprofv3 kernel statistics (ns)"
+    echo
+    echo '```'
+    cat $(find $D/stats -name '*kernel_stats.csv' | head -1)
+    echo '```'
+} > $OUT/access_pattern_1024.md
