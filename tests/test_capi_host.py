@@ -114,3 +114,13 @@ def test_invalid_arguments_are_rejected_without_a_device():
     assert b.value >= 2 * 256 * 1024 * 1024 * 4
     assert L.rlbm_set_waves(h, 17) == R.RLBM_EINVAL
     assert L.rlbm_destroy(h) == R.RLBM_OK
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """No fallback: without the built library every entry raises."""
+    monkeypatch.setattr(R, "_L", None)
+    monkeypatch.setattr(R, "SO_PATH", str(tmp_path / "librlbm.so"))
+    with pytest.raises(ImportError, match="not built"):
+        R.lib()
+    with pytest.raises(ImportError, match="not built"):
+        R.Solver(4, 16, 3)
