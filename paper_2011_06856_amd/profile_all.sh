@@ -29,6 +29,20 @@ run stream_collide_f32_circular_1024 "k_stream_collide<float, float, 3, 64>" 214
 run push_step_f32_quadrant_2048 "k_push_step<float, 5, 8, false>" 51539607552 \
     "--workload quadrant --side 2048 --steps 20" "--workload quadrant --side 2048 --steps 3"
 
+# The 48-problem batch (FP32, the library's default work-group shape and
+# mode, one graph replay per step): kernel statistics only, with the kernel
+# time of one step summed over the launches a step makes.
+D=$OUT/raw/batch48
+mkdir -p $D
+SV=$(python3 -c "import workloads as W; print(sum(p['Np'] * p['K'] * p['nx'] * p['ny'] for p in W.batch_problems(48, seed=0, steps=1)))")
+timeout -s KILL 180 rocprofv3 --kernel-trace --stats -d $D/stats -o run --output-format csv -- \
+    python3 -m paper_2011_06856_amd.profile_run --workload batch48 --steps 40 > $D.out.txt
+python3 -m paper_2011_06856_amd.profile_summary --stats $D/stats --name batch_step_f32_batch48 \
+    --kernel k_batch_step --launch-bytes 0 --out-dir $OUT \
+    --step-kernels k_batch_step,k_batch_flat,k_push_batch,k_reset_counters --steps 40 --sv-per-step $SV \
+    --command "rocprofv3 --kernel-trace --stats -- python3 -m paper_2011_06856_amd.profile_run --workload batch48 --steps 40 (bash paper_2011_06856_amd/profile_all.sh)"
+{ echo; echo "Program output: \`$(grep profile_run: $D.out.txt)\`"; } >> $OUT/batch_step_f32_batch48.md
+
 # The memory ceiling of the tile kernel's access pattern without its
 # arithmetic (probes/access_pattern.hip): its own event timing and the
 # rocprofv3 kernel statistics, in OUT/access_pattern_1024.md.

@@ -3,7 +3,9 @@
 Runs `--steps` steps of the circular-shock workload (side^2 periodic grid,
 Np=4 x K=64, order 3, Kn=0.01) or, with `--workload quadrant`, of the
 quadrant Riemann problem (side^2, Np=6 x K=256, order 5, Kn=10) at the given
-precision, then a device-to-device
+precision, or, with `--workload batch48`, of the 48-problem batch (FP32, one
+graph replay per step; `--waves` sets its work-group shape, else the
+library's default), then a device-to-device
 copy of exactly `--copy-mib` MiB (read once, written once) whose FETCH_SIZE /
 WRITE_SIZE readings calibrate the counters to bytes.
 
@@ -20,6 +22,16 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
+def copy_calibration(mib):
+    """One device copy of exactly `mib` MiB: read once, written once."""
+    import torch
+    n = mib * 1024 * 1024 // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=20)
@@ -27,12 +39,24 @@ def main():
     ap.add_argument("--side", type=int, default=1024)
     ap.add_argument("--Kn", type=float, default=0.01)
     ap.add_argument("--copy-mib", type=int, default=1024)
-    ap.add_argument("--workload", default="circular", choices=["circular", "quadrant"])
+    ap.add_argument("--workload", default="circular", choices=["circular", "quadrant", "batch48"])
     ap.add_argument("--waves", type=int, default=0)
     a = ap.parse_args()
     import torch
     import workloads as W
     from paper_2011_06856_amd import rlbm
+    if a.workload == "batch48":
+        b = rlbm.Batch(W.batch_problems(48, seed=0, steps=a.steps), precision="f32")
+        if a.waves:
+            b.set_waves(a.waves)
+        b.step(a.steps)
+        torch.cuda.synchronize()
+        what = "batch48 (mode %s, %d waves, %d site-velocity updates a step)" % (b.get_mode(), b.get_waves(), b.nsv)
+        del b
+        torch.cuda.empty_cache()
+        copy_calibration(a.copy_mib)
+        print("profile_run: %d steps of %s, then one %d MiB device copy" % (a.steps, what, a.copy_mib), flush=True)
+        return
     if a.workload == "circular":
         cfg = W.circular_shock(a.side, Kn=a.Kn, steps=a.steps)
     else:
@@ -43,11 +67,7 @@ def main():
         s.set_waves(a.waves)
     s.step(a.steps)
     torch.cuda.synchronize()
-    n = a.copy_mib * 1024 * 1024 // 4
-    src = torch.ones(n, dtype=torch.float32, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
+    copy_calibration(a.copy_mib)
     print("profile_run: %d steps of %s (%s), then one %d MiB device copy" % (a.steps, cfg["name"], a.precision,
                                                                           a.copy_mib), flush=True)
 

@@ -6,7 +6,9 @@ Usage:
         --launch-bytes 2147483648
 
 Writes profiles/<name>.md (kernel timing table, counter readings, the copy
-calibration factors and the derived HBM traffic per launch) and
+calibration factors and the derived HBM traffic per launch; without --fetch
+and --write the timing table only, and with --step-kernels the kernel time
+of one step summed over the kernels a step launches) and
 profiles/<name>.json, which bench.py reads to fill its `traffic` field while
 the kernel source is unchanged (sha256 of the kernel sources recorded here).
 """
@@ -53,19 +55,22 @@ def counter_per_kernel(d, counter):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--stats", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
     ap.add_argument("--name", required=True)
     ap.add_argument("--command", required=True)
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--kernel", default="k_stream_collide")
     ap.add_argument("--launch-bytes", type=float, required=True, help="algorithmic bytes per launch")
     ap.add_argument("--out-dir", default=os.path.join(ROOT, "profiles"))
+    ap.add_argument("--step-kernels", help="comma-separated kernel names whose launches make up one step")
+    ap.add_argument("--steps", type=int, help="steps the traced run took (with --step-kernels)")
+    ap.add_argument("--sv-per-step", type=float, help="site-velocity updates of one step (with --step-kernels)")
     a = ap.parse_args()
 
     stats = _rows(a.stats, "kernel_stats.csv")
-    fetch = counter_per_kernel(a.fetch, "FETCH_SIZE")
-    write = counter_per_kernel(a.write, "WRITE_SIZE")
+    fetch = counter_per_kernel(a.fetch, "FETCH_SIZE") if a.fetch else {}
+    write = counter_per_kernel(a.write, "WRITE_SIZE") if a.write else {}
     copy_kib = a.copy_mib * 1024.0
 
     def pick(d, key):
@@ -93,19 +98,35 @@ def main():
         lines.append("| %s | %s | %.1f | %.1f | %.1f | %.1f |" % (nm, r["Calls"], float(r["AverageNs"]) / 1e3,
                                                                 float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
                                                                 float(r["Percentage"])))
-    lines += ["", "## HBM counters (rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE; KiB per dispatch)", "",
-              "| quantity | value |", "|---|---|",
-              "| calibration copy size | %d MiB read + %d MiB written |" % (a.copy_mib, a.copy_mib),
-              "| FETCH_SIZE of the copy | %s KiB -> factor %s |" % (cf, "%.4f" % f_fac if f_fac else "n/a"),
-              "| WRITE_SIZE of the copy | %s KiB -> factor %s |" % (cw, "%.4f" % w_fac if w_fac else "n/a"),
-              "| %s FETCH_SIZE (avg of %d) | %s KiB |" % (a.kernel, len(kf), "%.1f" % kf_avg if kf_avg else "n/a"),
-              "| %s WRITE_SIZE (avg of %d) | %s KiB |" % (a.kernel, len(kw), "%.1f" % kw_avg if kw_avg else "n/a"),
-              "| traffic per launch (scaled) | %s bytes |" % ("%.4g" % traffic if traffic else "n/a"),
-              "| algorithmic bytes per launch | %.4g |" % a.launch_bytes,
-              "| traffic / algorithmic | %s |" % ("%.3f" % (traffic / a.launch_bytes) if traffic else "n/a"),
-              "| avg launch duration | %s us |" % ("%.1f" % (avg_ns / 1e3) if avg_ns else "n/a"),
-              "| algorithmic GB/s at that duration | %s |" % ("%.0f" % (a.launch_bytes / avg_ns) if avg_ns else "n/a"),
-              "", "Kernel sources sha256: `%s`" % kernel_source_hash(), ""]
+    lines += [""]
+    if a.fetch and a.write:
+        lines += ["## HBM counters (rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE; KiB per dispatch)", "",
+                  "| quantity | value |", "|---|---|",
+                  "| calibration copy size | %d MiB read + %d MiB written |" % (a.copy_mib, a.copy_mib),
+                  "| FETCH_SIZE of the copy | %s KiB -> factor %s |" % (cf, "%.4f" % f_fac if f_fac else "n/a"),
+                  "| WRITE_SIZE of the copy | %s KiB -> factor %s |" % (cw, "%.4f" % w_fac if w_fac else "n/a"),
+                  "| %s FETCH_SIZE (avg of %d) | %s KiB |" % (a.kernel, len(kf), "%.1f" % kf_avg if kf_avg else "n/a"),
+                  "| %s WRITE_SIZE (avg of %d) | %s KiB |" % (a.kernel, len(kw), "%.1f" % kw_avg if kw_avg else "n/a"),
+                  "| traffic per launch (scaled) | %s bytes |" % ("%.4g" % traffic if traffic else "n/a"),
+                  "| algorithmic bytes per launch | %.4g |" % a.launch_bytes,
+                  "| traffic / algorithmic | %s |" % ("%.3f" % (traffic / a.launch_bytes) if traffic else "n/a"),
+                  "| avg launch duration | %s us |" % ("%.1f" % (avg_ns / 1e3) if avg_ns else "n/a"),
+                  "| algorithmic GB/s at that duration | %s |" % ("%.0f" % (a.launch_bytes / avg_ns) if avg_ns else "n/a"),
+                  ""]
+    if a.step_kernels and a.steps and a.sv_per_step:
+        names = a.step_kernels.split(",")
+        step_rows = [r for r in stats if any(k in r["Name"] for k in names)]
+        per_step_ns = sum(float(r["TotalDurationNs"]) for r in step_rows) / a.steps
+        lines += ["## One step", "",
+                  "| quantity | value |", "|---|---|",
+                  "| kernels of a step | %s |" % ", ".join("%s (%s calls)" % (
+                      r["Name"].replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0], r["Calls"])
+                      for r in step_rows),
+                  "| kernel time per step (sum over those kernels / %d steps) | %.1f us |" % (a.steps, per_step_ns / 1e3),
+                  "| site-velocity updates per step | %.6g |" % a.sv_per_step,
+                  "| GSVUPS at that time | %.1f |" % (a.sv_per_step / per_step_ns),
+                  "| algorithmic GB/s at 8 B a site-velocity | %.0f |" % (8.0 * a.sv_per_step / per_step_ns), ""]
+    lines += ["Kernel sources sha256: `%s`" % kernel_source_hash(), ""]
     os.makedirs(a.out_dir, exist_ok=True)
     md = os.path.join(a.out_dir, a.name + ".md")
     open(md, "w").write("\n".join(lines))
