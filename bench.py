@@ -65,25 +65,69 @@ def gpu_run(cfg, steps, warmup, precision, waves, keep_fields=False):
     return out
 
 
-def cpu_baseline(precision_unused, budget_s):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(budget_s):
     """The FP64 oracle on a bounded sample: the same quadrature and state on a
     256 x 256 grid (Kn = 0.01 with tau scaled to the side), steps sized to the
-    budget after one timed probe step."""
+    budget after one timed probe step; once on all the host threads OpenMP
+    gets, then on one (with a third of the budget)."""
     import oracle as O
     side = 256
     cfg = W.circular_shock(side, Kn=0.01, steps=1)
     q = O.Quadrature(cfg["Np"], cfg["K"], cfg["N"])
-    sim = O.Sim(q, side, side, *cfg["fields"], tau=cfg["tau"], dt=cfg["dt"])
-    t0 = time.perf_counter()
-    sim.step(1)
-    probe = time.perf_counter() - t0
-    nsteps = max(1, int(budget_s / max(probe, 1e-3)))
-    t0 = time.perf_counter()
-    sim.step(nsteps)
-    dt = time.perf_counter() - t0
-    sv = side * side * q.nvel * nsteps
-    return dict(value=sv / dt / 1e9, unit="GSVUPS", cores=O.num_threads(), kind="oracle",
-                sample="%dx%d grid, Np=4 x K=64 (256 velocities), order 3, Kn=0.01, %d steps, FP64" % (side, side, nsteps))
+
+    def leg(budget):
+        sim = O.Sim(q, side, side, *cfg["fields"], tau=cfg["tau"], dt=cfg["dt"])
+        t0 = time.perf_counter()
+        sim.step(1)
+        probe = time.perf_counter() - t0
+        nsteps = max(1, int(budget / max(probe, 1e-3)))
+        t0 = time.perf_counter()
+        sim.step(nsteps)
+        dt = time.perf_counter() - t0
+        return side * side * q.nvel * nsteps / dt / 1e9, nsteps
+
+    cores = O.num_threads()
+    v_all, n_all = leg(budget_s)
+    O.set_threads(1)
+    v_one, n_one = leg(budget_s / 3.0)
+    O.set_threads(cores)
+    sample = "%dx%d grid, Np=4 x K=64 (256 velocities), order 3, Kn=0.01, FP64" % (side, side)
+    return dict(value=v_all, unit="GSVUPS", cores=cores, kind="oracle",
+                sample="%s, %d steps" % (sample, n_all), cpu_model=cpu_model(), host_threads=os.cpu_count(),
+                single_core={"value": v_one, "unit": "GSVUPS", "cores": 1, "sample": "%s, %d steps" % (sample, n_one)})
+
+
+def copy_bandwidth(nbytes=2 << 30, iters=10):
+    """Device-to-device copy rate on this GPU, measured in the same run: torch's
+    copy of nbytes between two HBM buffers, bytes read plus bytes written per
+    second (GB/s), the best of `iters` event-timed copies."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    best = None
+    for _ in range(iters):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (best * 1e-3) / 1e9
 
 
 def batched_form(a):
@@ -278,9 +322,13 @@ def main():
                      "algorithmic_bytes_per_sv": BYTES_PER_SV[a.precision],
                      "avg_launch_ms": launch_ms},
     }
+    print("bench: copy bandwidth", file=sys.stderr, flush=True)
+    cb = copy_bandwidth()
+    out["roofline"]["copy_measured"] = cb
+    out["roofline"]["frac_of_copy"] = achieved / cb
     if not a.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(a.precision, a.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(a.cpu_budget)
     print(json.dumps(out), flush=True)
 
 

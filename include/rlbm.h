@@ -46,7 +46,7 @@ enum {
     RLBM_ESTATE = -5    /* call out of order (e.g. step before init_fields) */
 };
 
-enum { RLBM_F64 = 0, RLBM_F32 = 1, RLBM_BF16DEV = 2 };   /* population storage */
+enum { RLBM_F64 = 0, RLBM_F32 = 1 };                     /* population storage */
 enum { RLBM_BC_PERIODIC = 0, RLBM_BC_CLAMP = 1 };         /* per axis */
 enum { RLBM_KERNEL_AUTO = 0, RLBM_KERNEL_TILE = 1, RLBM_KERNEL_PUSH = 2 };   /* step kernel */
 
@@ -75,7 +75,10 @@ int rlbm_nvel(rlbm_ctx ctx);
 int rlbm_get_quadrature(rlbm_ctx ctx, double* p, double* theta, double* w);
 
 /* Device workspace in bytes needed by rlbm_init_fields for an nx x ny grid at
- * the given precision (two population buffers plus per-site scratch). */
+ * the given precision: two population buffers of nvel + 1 planes, the field
+ * outputs (4 doubles per site), the partial charges, and the two partial-sum
+ * buffers of the push kernel (3 row slots x 8 moments per site plus a halo
+ * per tile edge), present whichever step kernel is used. */
 int rlbm_workspace_bytes(rlbm_ctx ctx, int nx, int ny, int precision, size_t* bytes);
 
 /*
@@ -92,14 +95,18 @@ int rlbm_workspace_bytes(rlbm_ctx ctx, int nx, int ny, int precision, size_t* by
  *                 must stay in [0, 1]).
  *   bc_x, bc_y    RLBM_BC_PERIODIC or RLBM_BC_CLAMP (zero-gradient: the
  *                 upwind neighbour outside the grid is the edge cell).
- *   precision     RLBM_F64 or RLBM_F32 population storage; RLBM_BF16DEV stores
- *                 f - f_eq in bfloat16 with per-site equilibrium coefficients.
+ *   precision     RLBM_F64 or RLBM_F32 population storage.
  *   d_workspace   device memory of at least rlbm_workspace_bytes() bytes,
  *                 256-byte aligned, owned by the caller (e.g. a torch tensor)
  *                 and alive until rlbm_destroy; NULL lets the library
  *                 allocate and own it.
  *   hip_stream    hipStream_t for all work of this context; NULL = default.
- * May be called again to restart a context (same or different grid).
+ * Builds the device tables of both step kernels (library-owned, freed by the
+ * next rlbm_init_fields or rlbm_destroy) and the initial populations;
+ * synchronises the stream.  May be called again to restart a context (same
+ * or different grid).  Any failure after the argument checks leaves the
+ * context without fields: rlbm_step and rlbm_moments then return
+ * RLBM_ESTATE until a call succeeds.
  */
 int rlbm_init_fields(rlbm_ctx ctx, int nx, int ny,
                      const double* n, const double* T, const double* ux, const double* uy,
@@ -109,9 +116,14 @@ int rlbm_init_fields(rlbm_ctx ctx, int nx, int ny,
 /*
  * Advance nsteps >= 0 time steps (Eq. discrete-rbe), one fused
  * stream-and-collide launch per step, asynchronously on the context's
- * stream.  Allocates nothing.  Non-physical sites (no timelike Landau
- * eigenvector, n <= 0 or eps <= 0) are streamed without collision and raise a
- * sticky device flag reported by the next rlbm_moments.
+ * stream.  Allocates nothing and makes no synchronising call, so the
+ * launches can be captured into a HIP graph: the two population buffers
+ * alternate, so a graph of an even number of steps replays correctly any
+ * number of times (the push kernel's partial sums must be valid first: one
+ * eager step after rlbm_init_fields, rlbm_set_populations or
+ * rlbm_set_kernel).  Non-physical sites (no timelike Landau eigenvector,
+ * n <= 0 or eps <= 0) are streamed without collision and raise a sticky
+ * device flag reported by the next rlbm_moments.
  */
 int rlbm_step(rlbm_ctx ctx, int nsteps);
 
@@ -134,9 +146,8 @@ int rlbm_moments(rlbm_ctx ctx, double* n, double* eps, double* ux, double* uy, d
 
 /* Checkpoint: copy the current populations (storage precision, layout
  * f[v][y][x]) to / from a caller-owned host buffer of exactly
- * nvel * nx * ny * element-size bytes (8 for F64, 4 for F32, 2 for BF16DEV
- * deviations followed by the per-site coefficients); other sizes give
- * RLBM_EINVAL.  Synchronous. */
+ * nvel * nx * ny * element-size bytes (8 for F64, 4 for F32); other sizes
+ * give RLBM_EINVAL.  Synchronous. */
 int rlbm_populations_bytes(rlbm_ctx ctx, size_t* bytes);
 int rlbm_get_populations(rlbm_ctx ctx, void* host, size_t bytes);
 int rlbm_set_populations(rlbm_ctx ctx, const void* host, size_t bytes);
@@ -155,10 +166,10 @@ int rlbm_set_waves(rlbm_ctx ctx, int waves);
  *                     values of 64 sites before their collision;
  *   RLBM_KERNEL_PUSH  each wave runs through all velocities of 64 sites once;
  *                     its moments come from partial sums pushed by the
- *                     previous step (13 slots x 8 moments per site, kept in
- *                     two library-owned device buffers allocated on first
- *                     use; recomputed after any external change of the
- *                     populations);
+ *                     previous step (3 row slots x 8 moments per site plus a
+ *                     halo per tile edge, in two buffers of the workspace;
+ *                     recomputed by the next rlbm_step after any external
+ *                     change of the populations);
  *   RLBM_KERNEL_AUTO  (default) PUSH from 320 velocities on, else TILE
  *                     (measured crossover between 256 and 384).
  * The results agree to rounding.  rlbm_get_kernel returns the kernel that

@@ -61,6 +61,7 @@ def _lib():
         L.orc_sim_set_f.argtypes = [ctypes.c_void_p, _dp]
         L.orc_sim_nonphys.restype = ctypes.c_long
         L.orc_sim_nonphys.argtypes = [ctypes.c_void_p]
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         _L = L
     return _L
 
@@ -72,6 +73,11 @@ def _ptr(a):
 def num_threads():
     """OpenMP threads the oracle uses."""
     return int(_lib().orc_num_threads())
+
+
+def set_threads(n):
+    """Use n OpenMP threads from now on."""
+    _lib().orc_set_threads(int(n))
 
 
 class Quadrature:

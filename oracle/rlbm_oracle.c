@@ -633,3 +633,6 @@ void orc_sim_set_f(orc_sim* s, const double* f)
 long orc_sim_nonphys(const orc_sim* s) { return s->nonphys; }
 
 int orc_num_threads(void) { return omp_get_max_threads(); }
+
+/* Threads of the parallel loops that follow (the benchmark's single-core leg). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }

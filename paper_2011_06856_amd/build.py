@@ -17,19 +17,23 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Wall", "-Wno-unused-result", "-Wno-unknown-warning-option"]
 
 
-def build(verbose=False, out=SO, defines=()):
-    """Compile the library to `out`; `defines` are extra -D flags (variants)."""
-    objs = []
+def build(verbose=False, out=SO):
+    """Compile the library to `out` (the sources in parallel)."""
+    from concurrent.futures import ThreadPoolExecutor
+    tag = "%d_%x" % (os.getpid(), abs(hash(out)) & 0xffffff)
+    jobs = []
     for src in SOURCES:
-        path = os.path.join(CSRC, src)
-        tag = "%d_%x" % (os.getpid(), abs(hash((out, tuple(defines)))) & 0xffffff)
         obj = os.path.join(CSRC, src.rsplit(".", 1)[0] + "." + tag + ".o")
-        lang = ["-x", "hip"]
-        cmd = [HIPCC] + FLAGS + ["-D" + d for d in defines] + lang + ["-c", path, "-o", obj]
-        if verbose:
+        cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+        jobs.append((cmd, obj))
+    if verbose:
+        for cmd, _ in jobs:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
-        objs.append(obj)
+    workers = max(1, min(len(jobs), os.cpu_count() or 1))
+    with ThreadPoolExecutor(workers) as ex:
+        for f in [ex.submit(subprocess.check_call, cmd) for cmd, _ in jobs]:
+            f.result()
+    objs = [obj for _, obj in jobs]
     tmp = out + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

@@ -24,20 +24,28 @@ size_t elem_size(int prec) { return prec == RLBM_F64 ? 8 : (prec == RLBM_F32 ? 4
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t f0, f1, fields, partials, flag, total;
+    size_t f0, f1, fields, partials, flag, pp0, pp1, total;
 };
 
-Layout layout(int nvel, long long S, int prec)
+// Workspace: two population buffers, the field outputs, the per-block
+// partial charges, the non-physical flag and the push kernel's two
+// partial-sum buffers (present whichever kernel is chosen, so that neither
+// rlbm_step nor rlbm_set_kernel allocates).
+Layout layout(int nvel, int nx, int ny, int prec)
 {
+    const long long S = (long long)nx * ny;
     Layout L;
     // nvel planes plus one spare plane written by the null table entries
     const size_t fb = align256((size_t)(nvel + 1) * S * elem_size(prec));
+    const size_t pb = align256(push_partial_bytes(prec, nx, ny));
     L.f0 = 0;
     L.f1 = L.f0 + fb;
     L.fields = L.f1 + fb;
     L.partials = L.fields + align256((size_t)4 * S * sizeof(double));
     L.flag = L.partials + align256((size_t)fields_blocks(S) * 4 * sizeof(double));
-    L.total = L.flag + 256;
+    L.pp0 = L.flag + 256;
+    L.pp1 = L.pp0 + pb;
+    L.total = L.pp1 + pb;
     return L;
 }
 
@@ -173,7 +181,7 @@ int rlbm_workspace_bytes(rlbm_ctx c, int nx, int ny, int precision, size_t* byte
 {
     if (!c || !bytes || nx < 1 || ny < 1) return fail(c, RLBM_EINVAL, "workspace_bytes: bad arguments");
     if (precision != RLBM_F64 && precision != RLBM_F32) return fail(c, RLBM_EINVAL, "unsupported precision");
-    *bytes = layout(c->q.nvel, (long long)nx * ny, precision).total;
+    *bytes = layout(c->q.nvel, nx, ny, precision).total;
     return RLBM_OK;
 }
 
@@ -196,10 +204,19 @@ int rlbm_init_fields(rlbm_ctx c, int nx, int ny, const double* n, const double* 
     for (long long i = 0; i < S; ++i)
         if (!(n[i] > 0.0) || !(T[i] > 0.0)) return fail(c, RLBM_EINVAL, "n and T must be positive");
 
+    // From here on the context holds no usable state until this call
+    // succeeds: a failure below leaves rlbm_step and rlbm_moments returning
+    // RLBM_ESTATE instead of running on freed or partial tables.
+    if (c->have_fields) (void)hipStreamSynchronize(c->st);
+    c->have_fields = 0;
+    c->pvalid = 0;
+    free_tables(c);
+    push_free(c);
+
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(c, e, "hipGetDevice");
-    const Layout L = layout(c->q.nvel, S, precision);
+    const Layout L = layout(c->q.nvel, nx, ny, precision);
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
 
     if (d_workspace) {
@@ -227,12 +244,13 @@ int rlbm_init_fields(rlbm_ctx c, int nx, int ny, const double* n, const double* 
     c->d_fields = reinterpret_cast<double*>(c->ws + L.fields);
     c->d_partials = reinterpret_cast<double*>(c->ws + L.partials);
     c->d_flag = reinterpret_cast<int*>(c->ws + L.flag);
+    c->pp[0] = c->ws + L.pp0;
+    c->pp[1] = c->ws + L.pp1;
     c->cur = 0;
+    c->pcur = 0;
     c->steps = 0;
 
     // device tables
-    free_tables(c);
-    push_free(c);
     std::vector<VelRec<double>> vd;
     build_vel_table(c->q, dt, vd);
     const size_t nv = c->q.nvel;
@@ -245,10 +263,17 @@ int rlbm_init_fields(rlbm_ctx c, int nx, int ny, const double* n, const double* 
         return hip_fail(c, e, "table upload");
     if ((e = hipMemcpy(c->d_Pc, c->q.Pc.data(), c->q.Pc.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(c, e, "table upload");
-    // kernel tables, padded with null entries (zero weights, spare plane)
+    // kernel tables, padded with null entries (zero weights, spare plane),
+    // for both step kernels
     {
         const int rc = upload_kernel_tables(c, vd, S, precision);
         if (rc != RLBM_OK) return rc;
+        std::string err;
+        const int prc = push_setup(c, err);
+        if (prc != RLBM_OK) {
+            push_free(c);
+            return fail(c, prc, "push kernel tables: " + err);
+        }
     }
 
     // upload the fields and build f = f_eq
@@ -298,14 +323,7 @@ int rlbm_step(rlbm_ctx c, int nsteps)
     if (!c->have_fields) return fail(c, RLBM_ESTATE, "rlbm_step before rlbm_init_fields");
     if (nsteps < 0) return fail(c, RLBM_EINVAL, "nsteps < 0");
     if (resolve_kernel(c) == RLBM_KERNEL_PUSH) {
-        if (!c->d_prec) {
-            std::string err;
-            const int rc = push_setup(c, err);
-            if (rc != RLBM_OK) {
-                push_free(c);
-                return fail(c, rc, "push kernel setup: " + err);
-            }
-        }
+        if (!c->d_prec) return fail(c, RLBM_ESTATE, "push kernel tables missing");
         hipError_t e;
         if (!c->pvalid && nsteps > 0) {
             if ((e = launch_push(c, true)) != hipSuccess) return hip_fail(c, e, "push partial sums launch");

@@ -262,11 +262,7 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
         const TC fn = f + om_ * (feq - f);
         TS* dst = reinterpret_cast<TS*>(wbase + ocb);
         // non-temporal: the next read of this plane is a step away
-#ifndef RLBM_TEMPORAL_STORE
         if (decltype(fast)::value || active) __builtin_nontemporal_store((TS)fn, dst);
-#else
-        if (decltype(fast)::value || active) *dst = (TS)fn;
-#endif
     };
     auto phase4 = [&](auto fast) __attribute__((always_inline)) {
 #pragma unroll

@@ -30,69 +30,14 @@ __device__ inline float ld_w(const unsigned short* p, long i) { return bf2f(p[i]
 
 // C[M][N] (+)= op(A) op(B), FP32 accumulate.  A is [M][K] (TA = false) or
 // [K][M] (TA = true); B is [K][N] (TB = false) or [N][K] (TB = true), of
-// element type TBt (float or bfloat16 bits).  64x64 output tile per
-// 256-thread work-group, 4x4 per thread, K in steps of 16 through LDS.
-template <bool TA, bool TB, typename TBt>
-__global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ A, const TBt* __restrict__ B,
-                                              float* __restrict__ C, int M, int N, int K, int accumulate)
-{
-    __shared__ float As[16][64 + 4];
-    __shared__ float Bs[16][64 + 4];
-    const int tid = threadIdx.x;
-    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-    const int tm = (tid / 16) * 4, tn = (tid % 16) * 4;
-    float acc[4][4] = {};
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        for (int e = tid; e < 16 * 64; e += 256) {
-            const int kk = e / 64, mm = e % 64;
-            const int gm = m0 + mm, gk = k0 + kk;
-            float va = 0.f;
-            if (gm < M && gk < K) va = TA ? A[(long)gk * M + gm] : A[(long)gm * K + gk];
-            As[kk][mm] = va;
-            const int gn = n0 + mm;
-            float vb = 0.f;
-            if (gn < N && gk < K) vb = TB ? ld_w(B, (long)gn * K + gk) : ld_w(B, (long)gk * N + gn);
-            Bs[kk][mm] = vb;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            float a[4], b[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[kk][tm + i];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tn + j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int gm = m0 + tm + i, gn = n0 + tn + j;
-            if (gm < M && gn < N) {
-                float* c = C + (long)gm * N + gn;
-                *c = accumulate ? *c + acc[i][j] : acc[i][j];
-            }
-        }
-}
-
-// The same product on the matrix cores: 64x64 output tile per 256-thread
+// element type TBt (float or bfloat16 bits).
+// On the matrix cores: 64x64 output tile per 256-thread
 // work-group, one 32x32 quadrant per wave, v_mfma_f32_32x32x2f32 (FP32
 // operands, FP32 accumulate; bfloat16 weights are widened exactly), K in
 // steps of 16 staged through LDS.  Operand layout of the instruction: lane l
 // supplies A[l % 32][k0 + l / 32] and B[k0 + l / 32][l % 32]; accumulator
 // register r of lane l is C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
 typedef float floatx16 __attribute__((ext_vector_type(16)));
-
-// 1: inference through the layer-by-layer kernels instead of the one-pass one.
-#ifndef RLBM_MLP_LAYERED
-#define RLBM_MLP_LAYERED 0
-#endif
 
 template <bool TA, bool TB, typename TBt>
 __global__ __launch_bounds__(256) void k_gemm_mfma(const float* __restrict__ A, const TBt* __restrict__ B,
@@ -462,11 +407,7 @@ template <bool TA, bool TB, typename TBt>
 hipError_t gemm(hipStream_t st, const float* A, const TBt* B, float* C, int M, int N, int K, int acc)
 {
     dim3 grid((N + 63) / 64, (M + 63) / 64);
-#ifdef RLBM_MLP_VALU_GEMM
-    hipLaunchKernelGGL((k_gemm<TA, TB, TBt>), grid, dim3(256), 0, st, A, B, C, M, N, K, acc);
-#else
     hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TBt>), grid, dim3(256), 0, st, A, B, C, M, N, K, acc);
-#endif
     return hipGetLastError();
 }
 
@@ -498,7 +439,7 @@ hipError_t forward(rlbm_mlp m, const float* X, int B, float* Y)
 
 hipError_t infer(rlbm_mlp m, const float* X, int B, float* Y)
 {
-    if (m->in != 64 || m->hid != 128 || m->out > 32 || m->nh + 1 > 9 || RLBM_MLP_LAYERED) return forward(m, X, B, Y);
+    if (m->in != 64 || m->hid != 128 || m->out > 32 || m->nh + 1 > 9) return forward(m, X, B, Y);
     FusedNet net;
     net.nl = m->nh + 1;
     net.out = m->out;

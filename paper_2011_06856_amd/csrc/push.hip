@@ -336,11 +336,7 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
                             fnew = f + om * (feq - f);
                             // non-temporal: the next read of this plane is a step away
                             T* dst = reinterpret_cast<T*>(outb + Rr.woff + ocb);
-#ifndef RLBM_TEMPORAL_STORE
                             if (FAST || active) __builtin_nontemporal_store(fnew, dst);
-#else
-                            if (FAST || active) *dst = fnew;
-#endif
                         }
                         // explicit FMAs: the step and the rebuild (INIT) must
                         // produce the same partial sums bit for bit
@@ -598,33 +594,38 @@ int upload_push_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, int precisi
         err = hipGetErrorString(e);
         return RLBM_EDEVICE;
     }
-    const int ntx = (c->nx + 63) / 64;
-    const size_t pbytes = ((size_t)3 * NMOM * S + (size_t)2 * 2 * 3 * NMOM * c->ny * ntx) * sizeof(T);
-    for (int b = 0; b < 2; ++b)
-        if ((e = hipMalloc(&c->pp[b], pbytes)) != hipSuccess) return RLBM_ENOMEM;
     (void)precision;
     return RLBM_OK;
 }
 
 }  // namespace
 
-// Drop the push kernel's tables and partial-sum buffers (capi.cpp calls it
-// when the grid or precision changes and at destroy).
+// Bytes of one partial-sum buffer of the push kernel: 3 row slots x 8
+// moments per site, plus the halo of the tiles' first and last columns
+// (2 edges x 2 directions x 3 rows x 8 moments per tile and row).
+size_t push_partial_bytes(int prec, int nx, int ny)
+{
+    const size_t es = prec == RLBM_F64 ? 8 : 4;
+    const size_t ntx = (size_t)(nx + 63) / 64;
+    return ((size_t)3 * NMOM * nx * ny + (size_t)2 * 2 * 3 * NMOM * ny * ntx) * es;
+}
+
+// Drop the push kernel's tables (capi.cpp calls it when the grid or
+// precision changes and at destroy).  The partial-sum buffers live in the
+// context's workspace.
 void push_free(rlbm_ctx c)
 {
     if (c->d_prec) (void)hipFree(c->d_prec);
     if (c->d_paddr) (void)hipFree(c->d_paddr);
     if (c->d_pseg) (void)hipFree(c->d_pseg);
-    for (int b = 0; b < 2; ++b)
-        if (c->pp[b]) (void)hipFree(c->pp[b]);
     c->d_prec = nullptr;
     c->d_paddr = nullptr;
     c->d_pseg = nullptr;
-    c->pp[0] = c->pp[1] = nullptr;
     c->pvalid = 0;
 }
 
-// Build the push tables and buffers for the context's grid and precision.
+// Build the push tables for the context's grid and precision (at
+// rlbm_init_fields, so that no step allocates).
 int push_setup(rlbm_ctx c, std::string& err)
 {
     push_free(c);
@@ -695,11 +696,8 @@ hipError_t launch_push(rlbm_ctx c, bool init)
 int push_prepare(rlbm_ctx c, std::string& err)
 {
     if (!c->d_prec) {
-        const int rc = push_setup(c, err);
-        if (rc != RLBM_OK) {
-            push_free(c);
-            return rc;
-        }
+        err = "push tables missing";
+        return RLBM_ESTATE;
     }
     if (!c->pvalid) {
         c->pcur = c->cur;

@@ -246,8 +246,9 @@ struct rlbm_ctx_s {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     long long steps = 0;
     double* d_corr = nullptr;            // learned correction: w p^2 {cos, sin} 2th per velocity
-    // push kernel (push.hip): segment-ordered velocity records, segments,
-    // double-buffered partial sums of the next step's moments
+    // push kernel (push.hip): segment-ordered velocity records, segments
+    // (library-owned), double-buffered partial sums of the next step's
+    // moments (in the workspace)
     int kern = 0;                        // RLBM_KERNEL_AUTO / _TILE / _PUSH
     void* d_prec = nullptr;
     void* d_paddr = nullptr;
@@ -278,6 +279,7 @@ hipError_t launch_batch_flat(int prec, int nmax, int waves, int items, const Bat
 // Push kernel (push.hip).
 void push_free(rlbm_ctx c);
 int push_setup(rlbm_ctx c, std::string& err);
+size_t push_partial_bytes(int prec, int nx, int ny);
 hipError_t launch_push(rlbm_ctx c, bool init);
 int push_prepare(rlbm_ctx c, std::string& err);
 int push_batch_wgs(rlbm_ctx c);

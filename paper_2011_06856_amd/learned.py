@@ -67,16 +67,6 @@ def rel_errors(a, ref):
     return out
 
 
-def spatial_stress(stats):
-    """(S, 3) raw T^xx, T^xy, T^yy from site statistics (n, eps, U^x, U^y,
-    pi^xx, pi^xy, pi^yy): T^ij = (eps + P) U^i U^j + P delta^ij + pi^ij with
-    P = eps / 2."""
-    import torch
-    eps, ux, uy = stats[:, 1], stats[:, 2], stats[:, 3]
-    w, P = 1.5 * eps, 0.5 * eps
-    return torch.stack([w * ux * ux + P + stats[:, 4], w * ux * uy + stats[:, 5], w * uy * uy + P + stats[:, 6]], 1)
-
-
 def collect(side, seeds, K_coarse, K_fine, steps, snapshots, rows_per_snapshot, net=None, seed_rows=0, log=None):
     """Training rows, teacher-forced.  A fine and a coarse run start from the
     same state and step in lockstep; after every coarse step its shear stress

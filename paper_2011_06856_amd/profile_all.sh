@@ -9,7 +9,6 @@
 # Writes OUT_DIR/raw/... (rocprofv3 CSV) and OUT_DIR/<name>.md/.json.
 set -e
 OUT=${1:-profile_out}
-ROOT=$(pwd)
 export TMPDIR=/tmp
 run() {   # name, kernel, launch bytes, stats args, counter args
     local name=$1 kernel=$2 bytes=$3 sargs=$4 cargs=$5
@@ -42,36 +41,3 @@ python3 -m paper_2011_06856_amd.profile_summary --stats $D/stats --name batch_st
     --step-kernels k_batch_step,k_batch_flat,k_push_batch,k_reset_counters --steps 40 --sv-per-step $SV \
     --command "rocprofv3 --kernel-trace --stats -- python3 -m paper_2011_06856_amd.profile_run --workload batch48 --steps 40 (bash paper_2011_06856_amd/profile_all.sh)"
 { echo; echo "Program output: \`$(grep profile_run: $D.out.txt)\`"; } >> $OUT/batch_step_f32_batch48.md
-
-# The memory ceiling of the tile kernel's access pattern without its
-# arithmetic (probes/access_pattern.hip): its own event timing and the
-# rocprofv3 kernel statistics, in OUT/access_pattern_1024.md.
-D=$OUT/raw/access_pattern
-mkdir -p $D
-/opt/rocm/bin/hipcc -O3 --offload-arch=gfx950 -Xclang -target-feature -Xclang -packed-fp32-ops \
-    $ROOT/paper_2011_06856_amd/probes/access_pattern.hip -o $D/access_pattern
-timeout -s KILL 180 rocprofv3 --kernel-trace --stats -d $D/stats -o run --output-format csv -- $D/access_pattern > $D/out.txt
-{
-    echo "# access_pattern_1024"
-    echo
-    echo "Command (run from the repository root on a machine with the GPU):"
-    echo
-    echo '```'
-    echo "hipcc -O3 --offload-arch=gfx950 -Xclang -target-feature -Xclang -packed-fp32-ops paper_2011_06856_amd/probes/access_pattern.hip -o access_pattern"
-    echo "rocprofv3 --kernel-trace --stats -- ./access_pattern   (bash paper_2011_06856_amd/profile_all.sh)"
-    echo '```'
-    echo
-    echo "f[v][y][x], FP32, 1024^2 sites x 256 planes (1.07 GB per buffer); GB/s counts 2 x 1.07 GB per launch."
-    echo
-    echo "## Event timing (the program's output)"
-    echo
-    echo '```'
-    cat $D/out.txt
-    echo '```'
-    echo
-    echo "## rocprofv3 kernel statistics (ns)"
-    echo
-    echo '```'
-    cat $(find $D/stats -name '*kernel_stats.csv' | head -1)
-    echo '```'
-} > $OUT/access_pattern_1024.md

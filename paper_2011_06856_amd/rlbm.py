@@ -11,14 +11,13 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# RLBM_LIBRARY may name another build of the same library (kernel variants)
-SO_PATH = os.environ.get("RLBM_LIBRARY") or os.path.join(_HERE, "librlbm.so")
+SO_PATH = os.path.join(_HERE, "librlbm.so")
 
 RLBM_OK, RLBM_EINVAL, RLBM_ENOMEM, RLBM_EDEVICE, RLBM_ENONPHYS, RLBM_ESTATE = 0, -1, -2, -3, -4, -5
-RLBM_F64, RLBM_F32, RLBM_BF16DEV = 0, 1, 2
+RLBM_F64, RLBM_F32 = 0, 1
 RLBM_BC_PERIODIC, RLBM_BC_CLAMP = 0, 1
-PRECISIONS = {"f64": RLBM_F64, "f32": RLBM_F32, "bf16dev": RLBM_BF16DEV}
-ELEM_BYTES = {RLBM_F64: 8, RLBM_F32: 4, RLBM_BF16DEV: 2}
+PRECISIONS = {"f64": RLBM_F64, "f32": RLBM_F32}
+ELEM_BYTES = {RLBM_F64: 8, RLBM_F32: 4}
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _vp = ctypes.c_void_p
@@ -224,12 +223,14 @@ class Solver:
             workspace = torch.empty(nbytes, dtype=torch.uint8, device=device or "cuda")
         if stream is None:
             stream = torch.cuda.current_stream(workspace.device)
-        self.workspace, self.stream = workspace, stream
-        self._keep = (n, T, ux, uy)
-        self._check(lib().rlbm_init_fields(self._h, nx, ny, _p(n), _p(T), _p(ux), _p(uy), float(tau), float(dt),
-                                           int(bcx), int(bcy), prec, _vp(workspace.data_ptr()),
-                                           _vp(stream.cuda_stream)))
-        self.nx, self.ny, self.precision = nx, ny, prec
+        rc = lib().rlbm_init_fields(self._h, nx, ny, _p(n), _p(T), _p(ux), _p(uy), float(tau), float(dt),
+                                    int(bcx), int(bcy), prec, _vp(workspace.data_ptr()), _vp(stream.cuda_stream))
+        # the context refers to the new workspace only after a successful
+        # call; after a failed one it holds no fields and uses no workspace
+        if rc == RLBM_OK:
+            self.workspace, self.stream = workspace, stream
+            self.nx, self.ny, self.precision = nx, ny, prec
+        self._check(rc)
         return self
 
     def step(self, nsteps=1):
@@ -256,11 +257,9 @@ class Solver:
         return b.value
 
     def get_populations(self):
-        dt = {RLBM_F64: np.float64, RLBM_F32: np.float32, RLBM_BF16DEV: np.uint8}[self.precision]
+        dt = {RLBM_F64: np.float64, RLBM_F32: np.float32}[self.precision]
         buf = np.empty(self.populations_bytes() // np.dtype(dt).itemsize, dtype=dt)
         self._check(lib().rlbm_get_populations(self._h, _vp(buf.ctypes.data), buf.nbytes))
-        if self.precision == RLBM_BF16DEV:
-            return buf
         return buf.reshape(self.nvel, self.ny, self.nx)
 
     def set_populations(self, f):

@@ -55,7 +55,12 @@ def test_traffic_is_reported_only_for_the_sources_it_was_taken_on(tmp_path, monk
 
 
 def test_cpu_baseline_reports_the_oracle_on_a_bounded_sample():
-    r = bench.cpu_baseline("f32", 0.0)
+    r = bench.cpu_baseline(0.0)
     assert r["kind"] == "oracle" and r["unit"] == "GSVUPS"
     assert r["value"] > 0 and r["cores"] >= 1
     assert "256x256" in r["sample"] and "1 steps" in r["sample"]
+    one = r["single_core"]
+    assert one["cores"] == 1 and one["value"] > 0
+    assert r["cpu_model"]
+    import oracle as O
+    assert O.num_threads() == r["cores"]      # the thread count is restored

@@ -111,8 +111,30 @@ def test_invalid_arguments_are_rejected_without_a_device():
     assert L.rlbm_moments(h, None, None, None, None, None) == R.RLBM_ESTATE
     b = ctypes.c_size_t()
     assert L.rlbm_workspace_bytes(h, 1024, 1024, 1, ctypes.byref(b)) == R.RLBM_OK
-    assert b.value >= 2 * 256 * 1024 * 1024 * 4
+    # two buffers of 256 + 1 planes, four FP64 field planes, and the push
+    # kernel's two partial-sum buffers (3 row slots x 8 moments per site)
+    assert b.value >= (2 * 257 * 4 + 4 * 8 + 2 * 3 * 8 * 4) * 1024 * 1024
+    assert L.rlbm_workspace_bytes(h, 1024, 1024, 2, ctypes.byref(b)) == R.RLBM_EINVAL   # no such precision
     assert L.rlbm_set_waves(h, 17) == R.RLBM_EINVAL
+    assert L.rlbm_destroy(h) == R.RLBM_OK
+
+
+def test_failed_initialisation_leaves_no_fields():
+    """A call of rlbm_init_fields that passes the argument checks and then
+    fails (here: no device) leaves the context without fields, so that a step
+    or a moments call is refused instead of running on freed tables."""
+    _lib_or_skip()
+    L = R.lib()
+    h = ctypes.c_void_p()
+    assert L.rlbm_init_quadrature(ctypes.byref(h), 3, 8, 2, 1) == R.RLBM_OK
+    n = np.ones(6)
+    rc = L.rlbm_init_fields(h, 3, 2, R._p(n), R._p(n), None, None, 1.0, 1.0, 0, 0, 1, None, None)
+    if rc == R.RLBM_OK:
+        L.rlbm_destroy(h)
+        pytest.skip("a device is present: the initialisation succeeded")
+    assert rc == R.RLBM_EDEVICE
+    assert L.rlbm_step(h, 1) == R.RLBM_ESTATE
+    assert L.rlbm_moments(h, None, None, None, None, None) == R.RLBM_ESTATE
     assert L.rlbm_destroy(h) == R.RLBM_OK
 
 

@@ -11,6 +11,7 @@ import pytest
 
 import oracle as O
 import workloads as W
+from fieldcheck import check_fields
 
 pytestmark = pytest.mark.gpu
 
@@ -75,10 +76,7 @@ def test_batch_fp64_matches_oracle():
         n, eps, ux, uy, _ = b.problem(i).moments()
         sim = O.Sim(O.Quadrature(p["Np"], p["K"], p["N"]), p["nx"], p["ny"], *p["fields"], tau=p["tau"], dt=p["dt"])
         sim.step(12)
-        rn, reps, rux, ruy = sim.fields()
-        assert np.abs(n - rn).max() <= 1e-12 * np.abs(rn).max()
-        assert np.abs(eps - reps).max() <= 1e-12 * np.abs(reps).max()
-        assert np.hypot(ux - rux, uy - ruy).max() <= 1e-12
+        check_fields((n, eps, ux, uy), sim.fields(), 1e-12, "batch_fp64_%d" % i)
 
 
 def test_graph_replays_match_eager_steps():

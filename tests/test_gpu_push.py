@@ -3,15 +3,14 @@ against the FP64 oracle and against the tile kernel, and the bookkeeping of
 its partial sums when the populations change outside a step.
 
 Tolerances as in test_gpu_parity: relative L-inf per field <= 1e-12 for FP64,
-<= 1e-4 for FP32 after 1000 steps; the flow through the four-velocity scale.
+<= 1e-4 for FP32 after 1000 steps; the flow as a vector (tests/fieldcheck.py).
 """
-import sys
-
 import numpy as np
 import pytest
 
 import oracle as O
 import workloads as W
+from fieldcheck import check_fields, say
 
 pytestmark = pytest.mark.gpu
 
@@ -25,25 +24,8 @@ def _rlbm():
     return rlbm
 
 
-def say(msg):
-    print(msg, file=sys.stderr, flush=True)
-
-
-def rel_linf(a, b):
-    den = np.abs(b).max()
-    return np.abs(a - b).max() / den if den > 1e-300 else np.abs(a - b).max()
-
-
 def check(got, exp, tol, label):
-    for k, name in enumerate(("n", "eps")):
-        err = rel_linf(got[k], exp[k])
-        say("%s %s rel_linf=%.3e" % (label, name, err))
-        assert err <= tol, (label, name, err)
-    du = np.hypot(got[2] - exp[2], got[3] - exp[3]).max()
-    umax = np.hypot(exp[2], exp[3]).max()
-    err = du / np.sqrt(1.0 + 2.0 * umax * umax)
-    say("%s u rel=%.3e" % (label, err))
-    assert err <= tol, (label, "u", err)
+    check_fields(got, exp, tol, label)
 
 
 def gpu(rl, kernel, Np, K, N, nx, ny, fld, tau, dt, steps, prec="f64", bcx=0, bcy=0):
@@ -154,19 +136,39 @@ def test_partial_sums_follow_external_changes():
 
 def test_push_fp32_matches_oracle_after_1000_steps():
     """FP32 populations, Np=4 x K=192 (768 velocities, where the automatic
-    choice is the push kernel), 1000 steps, Kn = 0.01 and 1, on a 48 x 40
-    periodic grid."""
+    choice is the push kernel), 1000 steps, Kn = 0.01 and 1, on a 200 x 16
+    periodic grid: four tile columns (the middle two on the interior load
+    path, partial sums crossing every tile edge through the halo) and four
+    4-row work-group bands."""
     rl = _rlbm()
-    nx, ny = 48, 40
+    nx, ny = 200, 16
     for Kn in (0.01, 1.0):
         tau = W.tau_of(Kn, nx)
-        fld = W.disc(nx, ny, nx / 6, seed=11)
+        fld = W.disc(nx, ny, ny / 3, seed=11)
         say("case push_fp32_1000 Kn=%g" % Kn)
         args = (4, 192, 3, nx, ny, fld, tau, W.dt_of(tau), 1000)
         got, s = gpu(rl, "auto", *args, prec="f32")
         assert s.get_kernel() == "push"
         exp = oracle(*args)
         check(got, exp, 1e-4, "push_fp32_1000_kn%g" % Kn)
+
+
+@pytest.mark.timeout(400)
+def test_precision_form_quadrature_fp32_matches_oracle_after_1000_steps():
+    """The precision form's quadrature and order (Np=6 x K=256 = 1536
+    velocities, order 5, Kn = 10) with FP32 populations on the push kernel,
+    1000 steps of the quadrant problem on a 136 x 24 periodic grid (one
+    interior tile column), against the FP64 oracle at the 1e-4 tolerance."""
+    rl = _rlbm()
+    nx, ny = 136, 24
+    tau = W.tau_of(10.0, nx)
+    fld = W.quadrant(nx, ny, seed=0)
+    say("case precision_quadrature_fp32_1000 %dx%d" % (nx, ny))
+    args = (6, 256, 5, nx, ny, fld, tau, W.dt_of(tau), 1000)
+    got, s = gpu(rl, "auto", *args, prec="f32")
+    assert s.get_kernel() == "push"
+    exp = oracle(*args)
+    check(got, exp, 1e-4, "precision_quadrature_fp32_1000")
 
 
 def test_precision_form_full_size_fp32_against_fp64():

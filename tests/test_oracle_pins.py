@@ -262,6 +262,61 @@ def test_landau_flags_non_physical_state():
     assert not ok
 
 
+# --- Eq. ll-decomp: shear stress of the Landau-Lifshitz decomposition (site_stats) ----------
+
+def _boost(ux, uy):
+    """Lorentz boost Lambda^mu_nu taking the rest frame to four-velocity U."""
+    U = four_velocity(ux, uy)
+    g = U[0]
+    L = np.eye(3)
+    L[0, 0] = g
+    L[0, 1:] = L[1:, 0] = U[1:]
+    u2 = ux * ux + uy * uy
+    if u2 > 0:
+        L[1:, 1:] += (g - 1.0) * np.outer(U[1:], U[1:]) / u2
+    return L
+
+
+def test_site_stats_shear_vanishes_for_equilibria():
+    """f = f_eq(n, T, U) is an ideal fluid, T = (eps + P) U U - P eta: its
+    shear stress is zero, at rest and moving (Eq. ll-decomp)."""
+    q = O.Quadrature(4, 64, 3)
+    rng = np.random.default_rng(11)
+    for trial in range(12):
+        n, T = rng.uniform(0.2, 2.0), rng.uniform(0.5, 1.5)
+        ux, uy = (0.0, 0.0) if trial == 0 else rng.uniform(-0.8, 0.8, size=2)
+        st = O.site_stats(q.moments(q.feq(n, T, ux, uy)))
+        np.testing.assert_allclose(st[:4], [n, 2 * n * T, ux, uy], rtol=1e-12, atol=1e-13)
+        np.testing.assert_allclose(st[4:], 0.0, atol=1e-12 * n * T)
+
+
+def test_site_stats_recovers_a_prescribed_shear_stress():
+    """Build T^{mu nu} = (eps + P) U U - P eta + pi from a traceless spatial
+    shear stress given in the rest frame and boosted to U (so that pi U = 0),
+    with N^mu = n U^mu; the decomposition must return n, eps, U and the lab
+    frame's pi^{ij}.  A wrong enthalpy, pressure sign or index order fails
+    for moving frames."""
+    rng = np.random.default_rng(5)
+    for trial in range(16):
+        n, eps = rng.uniform(0.3, 2.0), rng.uniform(0.5, 3.0)
+        ux, uy = rng.uniform(-0.7, 0.7, size=2)
+        a, b = rng.uniform(-0.1, 0.1, size=2) * eps
+        pi_rest = np.array([[0.0, 0.0, 0.0], [0.0, a, b], [0.0, b, -a]])
+        L = _boost(ux, uy)
+        pi = L @ pi_rest @ L.T
+        U = four_velocity(ux, uy)
+        P = eps / 2.0
+        Tmn = (eps + P) * np.outer(U, U) - P * np.linalg.inv(ETA) + pi
+        assert np.allclose(pi @ ETA @ U, 0.0, atol=1e-14)             # orthogonal to U
+        assert abs(np.trace(ETA @ pi)) < 1e-14                          # traceless
+        N = n * U
+        mom = [N[0], N[1], N[2], Tmn[0, 0], Tmn[0, 1], Tmn[0, 2], Tmn[1, 1], Tmn[1, 2], Tmn[2, 2]]
+        st = O.site_stats(mom)
+        assert st is not None
+        np.testing.assert_allclose(st[:4], [n, eps, ux, uy], rtol=1e-12, atol=1e-13)
+        np.testing.assert_allclose(st[4:], [pi[1, 1], pi[1, 2], pi[2, 2]], atol=1e-12 * eps)
+
+
 # --- Eq. collision: conservation, equilibrium, relaxation rate --------------------------------
 
 def test_collision_conserves_charges_per_site():
