@@ -144,6 +144,25 @@ int rlbm_step_timed(rlbm_ctx ctx, int nsteps, double* ms);
  */
 int rlbm_moments(rlbm_ctx ctx, double* n, double* eps, double* ux, double* uy, double* charges);
 
+/*
+ * For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid allocation): the fields and charges of
+ * rlbm_moments, computed by the same kernel, into caller-owned DEVICE memory,
+ * asynchronously on the context's stream.
+ *   d_fields   device [4][ny][nx] doubles: n, eps, U^x, U^y (NaN at
+ *              non-physical sites), or NULL to skip;
+ *   d_charges  device [4] doubles: sum N^0, T^00, T^0x, T^0y, or NULL.
+ * Allocates nothing and makes no synchronising call: the per-block partial
+ * charges go to a fixed device scratch array of the library (2 MiB on each
+ * device it runs on, held until the process ends), which limits the grid to
+ * 16,777,216 sites (RLBM_EINVAL beyond).  Every call on one device shares
+ * that array, so calls that overlap in time on one device (other streams,
+ * other host threads) race: order them.  A non-physical site raises the
+ * context's sticky flag, reported by the next rlbm_moments.  RLBM_ESTATE
+ * before rlbm_init_fields.
+ */
+int rlbm_moments_device(rlbm_ctx ctx, double* d_fields, double* d_charges);
+
 /* Checkpoint: copy the current populations (storage precision, layout
  * f[v][y][x]) to / from a caller-owned host buffer of exactly
  * nvel * nx * ny * element-size bytes (8 for F64, 4 for F32); other sizes

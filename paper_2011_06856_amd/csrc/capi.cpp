@@ -216,6 +216,8 @@ int rlbm_init_fields(rlbm_ctx c, int nx, int ny, const double* n, const double* 
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(c, e, "hipGetDevice");
+    if (scratch_setup(dev) != RLBM_OK) return fail(c, RLBM_EDEVICE, "device scratch address");
+    c->dev = dev;
     const Layout L = layout(c->q.nvel, nx, ny, precision);
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
 
@@ -375,6 +377,22 @@ int rlbm_moments(rlbm_ctx c, double* n, double* eps, double* ux, double* uy, dou
                                  c->q.nvel, c->st);
     if (e != hipSuccess) return hip_fail(c, e, "fields launch");
     return fields_out(c, n, eps, ux, uy, charges);
+}
+
+// The fields and charges of rlbm_moments into caller-owned device memory,
+// asynchronously, with the partial charges in the fixed device scratch.
+int rlbm_moments_device(rlbm_ctx c, double* d_fields, double* d_charges)
+{
+    if (!c) return RLBM_EINVAL;
+    if (!c->have_fields) return fail(c, RLBM_ESTATE, "rlbm_moments_device before rlbm_init_fields");
+    if (c->S > scratch_max_sites())
+        return fail(c, RLBM_EINVAL, "rlbm_moments_device: grid larger than the device scratch allows (" +
+                                        std::to_string(scratch_max_sites()) + " sites)");
+    double* partials = static_cast<double*>(scratch_ptr(c->dev));
+    if (!partials) return fail(c, RLBM_ESTATE, "device scratch not set up");
+    const hipError_t e = launch_fields_charges(c->prec, c->f[c->cur], c->d_veld, d_fields ? d_fields : c->d_fields,
+                                               partials, d_charges, c->d_flag, c->nx, c->ny, c->q.nvel, c->st);
+    return e == hipSuccess ? RLBM_OK : hip_fail(c, e, "moments_device launch");
 }
 
 }  // extern "C"

@@ -18,6 +18,7 @@
 //      relaxes (Eq. collision, relaxing sign) and stores to the other buffer.
 // Velocities of a chunk beyond the register budget VPT are streamed twice
 // (recomputed in step 4) instead of being held.
+#include <mutex>
 #include <type_traits>
 
 #include "rlbm_internal.h"
@@ -667,6 +668,73 @@ hipError_t launch_fields(int prec, const void* f, const VelRec<double>* vel, dou
         hipLaunchKernelGGL((k_fields<float>), dim3(blocks), dim3(256), 0, st, (const float*)f, vel, out, partials, flag, S, nvel);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch of rlbm_moments_device: the per-block partial charges
+// of k_fields live in this array instead of the context's workspace, so that
+// the call needs no memory beyond its inputs and outputs.  Each device holds
+// its own copy; its address is taken once per device (scratch_setup, called
+// by rlbm_init_fields with the device current) and kept in scratch_addr.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int SCRATCH_BLOCKS = 65536;   // partial-charge blocks: grids up to 65536 x 256 sites
+constexpr int SCRATCH_DEVICES = 64;
+static __device__ __align__(256) double scratch[SCRATCH_BLOCKS * 4];
+void* scratch_addr[SCRATCH_DEVICES];
+std::mutex scratch_mu;
+
+// Sum of nb per-block partial charges [nb][4] into out[4], in FP64, one
+// work-group of 256 threads: a fixed strided order, then a tree.
+__global__ __launch_bounds__(256) void k_charges_sum(const double* __restrict__ partials, int nb,
+                                                     double* __restrict__ out)
+{
+    __shared__ double red[4][256];
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += 256)
+        for (int k = 0; k < 4; ++k) a[k] += partials[(size_t)b * 4 + k];
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = a[k];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) out[threadIdx.x] = red[threadIdx.x][0];
+}
+}  // namespace
+
+long long scratch_max_sites() { return (long long)SCRATCH_BLOCKS * 256; }
+
+int scratch_setup(int dev)
+{
+    if (dev < 0 || dev >= SCRATCH_DEVICES) return RLBM_EDEVICE;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (scratch_addr[dev]) return RLBM_OK;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return RLBM_EDEVICE;
+    scratch_addr[dev] = p;
+    return RLBM_OK;
+}
+
+void* scratch_ptr(int dev)
+{
+    if (dev < 0 || dev >= SCRATCH_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    return scratch_addr[dev];
+}
+
+// Fields of f into out (device [4][S], may be the context's own buffer) and
+// the charges into charges (device [4] or null), with the partial charges in
+// `partials` (the scratch array's device address); no allocation, no
+// synchronisation.
+hipError_t launch_fields_charges(int prec, const void* f, const VelRec<double>* vel, double* out, double* partials,
+                                 double* charges, int* flag, int nx, int ny, int nvel, hipStream_t st)
+{
+    hipError_t e = launch_fields(prec, f, vel, out, partials, flag, nx, ny, nvel, st);
+    if (e != hipSuccess || !charges) return e;
+    hipLaunchKernelGGL(k_charges_sum, dim3(1), dim3(256), 0, st, partials, fields_blocks((long long)nx * ny), charges);
     return hipGetLastError();
 }
 

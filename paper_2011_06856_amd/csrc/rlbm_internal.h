@@ -224,6 +224,7 @@ struct rlbm_ctx_s {
     HostQuad q;
     std::string err;
     int have_fields = 0;
+    int dev = -1;                        // device of the workspace (rlbm_init_fields)
     int nx = 0, ny = 0, prec = RLBM_F64, bcx = 0, bcy = 0;
     long long S = 0;
     double tau = 0, dt = 1, rate = 0;
@@ -269,6 +270,15 @@ hipError_t launch_stream_collide(int prec, int nmax, int waves, const SCParams& 
 hipError_t launch_fields(int prec, const void* f, const VelRec<double>* vel, double* out, double* partials,
                          int* flag, int nx, int ny, int nvel, hipStream_t st);
 hipError_t launch_landau_probe(const double* mom, double* out, int count, hipStream_t st);
+// The fixed device scratch of rlbm_moments_device (kernels.hip): its
+// address on a device is taken once (scratch_setup, device current) and
+// read back by scratch_ptr (null if not set up); grids up to
+// scratch_max_sites() sites.
+int scratch_setup(int dev);
+void* scratch_ptr(int dev);
+long long scratch_max_sites();
+hipError_t launch_fields_charges(int prec, const void* f, const VelRec<double>* vel, double* out, double* partials,
+                                 double* charges, int* flag, int nx, int ny, int nvel, hipStream_t st);
 hipError_t launch_batch_step(int prec, int nmax, int waves, int grid, const BatchDesc* descs, int nprob,
                              int* counters, const int* bounds, int parity, const double* Pc, int max_np,
                              hipStream_t st);

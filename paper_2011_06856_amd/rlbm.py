@@ -34,6 +34,7 @@ SIGNATURES = [
     ("rlbm_step", ctypes.c_int, [_vp, ctypes.c_int]),
     ("rlbm_step_timed", ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     ("rlbm_moments", ctypes.c_int, [_vp, _dp, _dp, _dp, _dp, _dp]),
+    ("rlbm_moments_device", ctypes.c_int, [_vp, _vp, _vp]),
     ("rlbm_populations_bytes", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
     ("rlbm_get_populations", ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
     ("rlbm_set_populations", ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
@@ -250,6 +251,17 @@ class Solver:
         if rc != RLBM_ENONPHYS or raise_nonphysical:
             self._check(rc)
         return n, eps, ux, uy, ch
+
+    def moments_device(self, fields=None, charges=None):
+        """rlbm_moments_device: fields (torch float64 tensor of 4 * ny * nx
+        elements on the context's device, or None) and charges (4 elements,
+        or None) are written asynchronously on the context's stream."""
+        import torch
+        for t, n in ((fields, 4 * self.nx * self.ny), (charges, 4)):
+            if t is not None and (t.dtype != torch.float64 or t.numel() != n or not t.is_contiguous()):
+                raise ValueError("moments_device: need a contiguous float64 tensor of %d elements" % n)
+        self._check(lib().rlbm_moments_device(self._h, None if fields is None else _vp(fields.data_ptr()),
+                                              None if charges is None else _vp(charges.data_ptr())))
 
     def populations_bytes(self):
         b = ctypes.c_size_t()
