@@ -95,8 +95,8 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
     const int NW = blockDim.x >> 6;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    TC* part = reinterpret_cast<TC*>(smem);            // [NW][NMOM][64]
-    TC* coef = part + NW * NMOM * 64;                   // [Np][NT][64]
+    double* part = reinterpret_cast<double*>(smem);    // [NW][NMOM][64]
+    TC* coef = reinterpret_cast<TC*>(part + NW * NMOM * 64);   // [Np][NT][64]
 
     const int ntx = (P.nx + 63) >> 6;
     const int band = tile / (ntx * P.band);
@@ -162,8 +162,12 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
     // 1. stream and accumulate moments, LB velocities' loads in flight at once
     TC fs[VPT];
     TC m[NMOM];
+    double md[NMOM];
 #pragma unroll
-    for (int j = 0; j < NMOM; ++j) m[j] = TC(0);
+    for (int j = 0; j < NMOM; ++j) {
+        m[j] = TC(0);
+        md[j] = 0.0;
+    }
     auto phase1 = [&](auto fast) __attribute__((always_inline)) {
 #pragma unroll
         for (int kb = 0; kb < VPT / LB; ++kb) {
@@ -176,6 +180,12 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
 #pragma unroll
                 for (int b = 0; b < LB; ++b)
                     load4(fast, (unsigned)(sg >> (8 * b)) & 3u, rnext(v0 + kb * LB + b), raw[b]);
+                // FP32: each batch's 8-term sums start from zero and are
+                // carried into FP64 accumulators (FP32 rounds only within
+                // a batch); FP64 accumulates directly
+                TC mb[NMOM];
+#pragma unroll
+                for (int j = 0; j < NMOM; ++j) mb[j] = sizeof(TC) == 4 ? TC(0) : m[j];
 #pragma unroll
                 for (int b = 0; b < LB; ++b) {
                     const int v = v0 + kb * LB + b;
@@ -183,7 +193,14 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
                     fs[kb * LB + b] = f;
                     CSRec& R = srec[v];
 #pragma unroll
-                    for (int j = 0; j < NMOM; ++j) m[j] += R.P[j] * f;
+                    for (int j = 0; j < NMOM; ++j) mb[j] += R.P[j] * f;
+                }
+#pragma unroll
+                for (int j = 0; j < NMOM; ++j) {
+                    if constexpr (sizeof(TC) == 4)
+                        md[j] += (double)mb[j];
+                    else
+                        m[j] = mb[j];
                 }
             }
         }
@@ -203,13 +220,13 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
 
     // 2. cross-wave reduction in FP64 and Landau frame
 #pragma unroll
-    for (int j = 0; j < NMOM; ++j) part[(w * NMOM + j) * 64 + lane] = m[j];
+    for (int j = 0; j < NMOM; ++j) part[(w * NMOM + j) * 64 + lane] = md[j] + (double)m[j];
     __syncthreads();
     double mom[9];
 #pragma unroll
     for (int j = 0; j < NMOM; ++j) {
         double s = 0.0;
-        for (int u = 0; u < NW; ++u) s += (double)part[(u * NMOM + j) * 64 + lane];
+        for (int u = 0; u < NW; ++u) s += part[(u * NMOM + j) * 64 + lane];
         mom[j] = s;
     }
     if (NMOM == 8) mom[8] = mom[3] - mom[6];
@@ -446,7 +463,7 @@ hipError_t launch_sc_t(int waves, const SCParams& p, hipStream_t st)
 {
     constexpr int NT = 2 * NM + 1;
     constexpr int NMOM = sizeof(TC) == 8 ? 9 : 8;
-    const size_t lds = (size_t)waves * NMOM * 64 * sizeof(TC) + (size_t)p.Np * NT * 64 * sizeof(TC);
+    const size_t lds = (size_t)waves * NMOM * 64 * sizeof(double) + (size_t)p.Np * NT * 64 * sizeof(TC);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     static size_t configured = 0;
     if (lds > 64 * 1024 && lds > configured) {
@@ -500,7 +517,7 @@ size_t batch_lds(int waves, int max_np)
 {
     constexpr int NT = 2 * NM + 1;
     constexpr int NMOM = sizeof(TC) == 8 ? 9 : 8;
-    return (size_t)waves * NMOM * 64 * sizeof(TC) + (size_t)max_np * NT * 64 * sizeof(TC);
+    return (size_t)waves * NMOM * 64 * sizeof(double) + (size_t)max_np * NT * 64 * sizeof(TC);
 }
 
 template <typename TS, typename TC, int NM, int VPT>
