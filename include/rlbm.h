@@ -47,7 +47,18 @@ enum {
 };
 
 enum { RLBM_F64 = 0, RLBM_F32 = 1 };                     /* population storage */
-enum { RLBM_BC_PERIODIC = 0, RLBM_BC_CLAMP = 1 };         /* per axis */
+/* Boundary condition per axis: what an upwind point outside the grid holds
+ * (the paper's box domain states none and names boundary conditions as the
+ * next step, Sec. 4):
+ *   PERIODIC  the point on the opposite side;
+ *   CLAMP     the edge cell's population (zero gradient: free outflow);
+ *   WALL      the target cell's population of the reversed velocity
+ *             (theta + pi, same shell): halfway bounce-back, conserving mass
+ *             and energy per cell; needs an even number of angles;
+ *   FIXED     the population the edge cell had at rlbm_init_fields (a
+ *             reservoir at the initial state: inflow and outflow).
+ * WALL and FIXED run on the tile kernel (RLBM_KERNEL_TILE). */
+enum { RLBM_BC_PERIODIC = 0, RLBM_BC_CLAMP = 1, RLBM_BC_WALL = 2, RLBM_BC_FIXED = 3 };   /* per axis */
 enum { RLBM_KERNEL_AUTO = 0, RLBM_KERNEL_TILE = 1, RLBM_KERNEL_PUSH = 2 };   /* step kernel */
 
 /*
@@ -93,8 +104,8 @@ int rlbm_workspace_bytes(rlbm_ctx ctx, int nx, int ny, int precision, size_t* by
  *                 streaming.  Kn = tau / L (Sec. 3.1).
  *   dt            time step in (0, 1] (the bilinear weights dt |v_x|, dt |v_y|
  *                 must stay in [0, 1]).
- *   bc_x, bc_y    RLBM_BC_PERIODIC or RLBM_BC_CLAMP (zero-gradient: the
- *                 upwind neighbour outside the grid is the edge cell).
+ *   bc_x, bc_y    RLBM_BC_PERIODIC, RLBM_BC_CLAMP, RLBM_BC_WALL (n_angle
+ *                 even) or RLBM_BC_FIXED, per axis (see the enum above).
  *   precision     RLBM_F64 or RLBM_F32 population storage.
  *   d_workspace   device memory of at least rlbm_workspace_bytes() bytes,
  *                 256-byte aligned, owned by the caller (e.g. a torch tensor)
@@ -190,9 +201,11 @@ int rlbm_set_waves(rlbm_ctx ctx, int waves);
  *                     recomputed by the next rlbm_step after any external
  *                     change of the populations);
  *   RLBM_KERNEL_AUTO  (default) PUSH from 320 velocities on, else TILE
- *                     (measured crossover between 256 and 384).
+ *                     (measured crossover between 256 and 384); TILE on a
+ *                     grid with a WALL or FIXED axis.
  * The results agree to rounding.  rlbm_get_kernel returns the kernel that
- * rlbm_step uses.  RLBM_EINVAL for an unknown kind.
+ * rlbm_step uses.  RLBM_EINVAL for an unknown kind, and for PUSH on a grid
+ * with a WALL or FIXED axis.
  */
 int rlbm_set_kernel(rlbm_ctx ctx, int kind);
 int rlbm_get_kernel(rlbm_ctx ctx, int* kind);
@@ -221,7 +234,8 @@ typedef struct {
  * RLBM_F64), each initialised to local equilibrium as by rlbm_init_fields,
  * with library-owned device memory; all work goes to hip_stream, which must
  * not be the null stream (graphs cannot capture it); NULL makes the batch
- * create and own a stream.  All problems must share the equilibrium order class (order <= 3,
+ * create and own a stream.  Boundaries: RLBM_BC_PERIODIC or RLBM_BC_CLAMP per
+ * axis.  All problems must share the equilibrium order class (order <= 3,
  * 4..5 or 6..7), since one kernel instance serves the launch.  RLBM_EINVAL as
  * for the single-problem calls.
  */

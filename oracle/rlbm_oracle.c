@@ -439,19 +439,43 @@ int orc_landau(const double* mom, double* out6)
 /* bilinear interpolation of Eq. interpolation, then Eq. collision)          */
 /* ------------------------------------------------------------------------- */
 
+/* Boundary condition per axis.  The paper uses a box domain without stating
+ * its boundaries and names boundary conditions as the next step (Sec. 4);
+ * beyond periodic and zero-gradient (clamp) edges, two kinds are defined
+ * here for an upwind point that falls outside the grid:
+ *   WALL   halfway bounce-back: the point takes the population of the
+ *          reversed velocity (theta + pi, same shell) at the target cell
+ *          itself, so what a cell sends toward the wall returns to it
+ *          reversed (mass and energy conserved per cell, momentum not);
+ *   FIXED  a reservoir: the point takes the initial population (the
+ *          truncated equilibrium of the initial fields) of the edge cell it
+ *          is clamped to, for ever (inflow at a fixed state; outflow of
+ *          whatever reaches the edge).
+ * A point across a wall takes the wall's value even where the other axis is
+ * FIXED. */
+enum { BC_PERIODIC = 0, BC_CLAMP = 1, BC_WALL = 2, BC_FIXED = 3 };
+
 typedef struct {
     const orc_quad* q;
-    int nx, ny, bcx, bcy;       /* bc: 0 periodic, 1 clamp (zero gradient) */
+    int nx, ny, bcx, bcy;       /* BC_* per axis */
     double tau, dt;
     double *f, *fs;             /* [nvel][ny][nx] */
+    double *f0;                 /* initial populations (FIXED edges), or NULL */
     long nonphys;
 } orc_sim;
 
 static int wrap(int i, int n, int bc)
 {
     if (i >= 0 && i < n) return i;
-    if (bc == 0) return ((i % n) + n) % n;
+    if (bc == BC_PERIODIC) return ((i % n) + n) % n;
     return i < 0 ? 0 : n - 1;
+}
+
+/* The reversed velocity of v: angle theta + pi on the same shell. */
+static int reversed(const orc_quad* q, int v)
+{
+    int i = v / q->K, j = v % q->K;
+    return i * q->K + (j + q->K / 2) % q->K;
 }
 
 static void site_eq(const orc_quad* q, double n, double T, double ux, double uy, double* out, long stride)
@@ -470,6 +494,8 @@ orc_sim* orc_sim_new(const orc_quad* q, int nx, int ny, const double* n, const d
                      const double* ux, const double* uy, double tau, double dt, int bcx, int bcy)
 {
     if (!q || nx < 1 || ny < 1) return NULL;
+    if (bcx < BC_PERIODIC || bcx > BC_FIXED || bcy < BC_PERIODIC || bcy > BC_FIXED) return NULL;
+    if ((bcx == BC_WALL || bcy == BC_WALL) && (q->K % 2)) return NULL;   /* no reversed velocity */
     orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
     s->q = q; s->nx = nx; s->ny = ny; s->bcx = bcx; s->bcy = bcy; s->tau = tau; s->dt = dt;
     long S = (long)nx * ny;
@@ -478,13 +504,17 @@ orc_sim* orc_sim_new(const orc_quad* q, int nx, int ny, const double* n, const d
     #pragma omp parallel for schedule(static)
     for (long i = 0; i < S; ++i)
         site_eq(q, n[i], T[i], ux ? ux[i] : 0.0, uy ? uy[i] : 0.0, s->f + i, S);
+    if (bcx == BC_FIXED || bcy == BC_FIXED) {
+        s->f0 = (double*)malloc(sizeof(double) * S * q->nvel);
+        memcpy(s->f0, s->f, sizeof(double) * S * q->nvel);
+    }
     return s;
 }
 
 void orc_sim_free(orc_sim* s)
 {
     if (!s) return;
-    free(s->f); free(s->fs); free(s);
+    free(s->f); free(s->fs); free(s->f0); free(s);
 }
 
 /* Streaming with bilinear interpolation from the upwind cell quad.  In
@@ -506,10 +536,24 @@ static void stream_pass(orc_sim* s)
             const double* fv = s->f + (long)v * S;
             double* ov = s->fs + (long)v * S;
             int y1 = wrap(y - sy, ny, s->bcy);
+            /* upwind points outside the grid (WALL and FIXED edges only) */
+            int yo = (y - sy < 0 || y - sy >= ny) && s->bcy >= BC_WALL;
+            const double* rv = s->f + (long)(s->bcx == BC_WALL || s->bcy == BC_WALL ? reversed(q, v) : v) * S;
+            const double* iv = s->f0 ? s->f0 + (long)v * S : fv;
             for (int x = 0; x < nx; ++x) {
                 int x1 = wrap(x - sx, nx, s->bcx);
+                int xo = (x - sx < 0 || x - sx >= nx) && s->bcx >= BC_WALL;
                 double f00 = fv[(long)y * nx + x], f10 = fv[(long)y * nx + x1];
                 double f01 = fv[(long)y1 * nx + x], f11 = fv[(long)y1 * nx + x1];
+                if (xo || yo) {
+                    int xw = xo && s->bcx == BC_WALL, yw = yo && s->bcy == BC_WALL;
+                    double back = rv[(long)y * nx + x];   /* reversed population of the target */
+                    /* FIXED: the initial population at the clamped point
+                     * (x1, y1 are clamped on a FIXED axis) */
+                    if (xo) f10 = xw ? back : iv[(long)y * nx + x1];
+                    if (yo) f01 = yw ? back : iv[(long)y1 * nx + x];
+                    f11 = (xw || yw) ? back : iv[(long)y1 * nx + x1];
+                }
                 ov[(long)y * nx + x] = (1 - ax) * (1 - ay) * f00 + ax * (1 - ay) * f10
                                      + (1 - ax) * ay * f01 + ax * ay * f11;
             }

@@ -237,6 +237,10 @@ int rlbm_batch_create(rlbm_batch* out, const rlbm_problem* probs, int count, int
     int nmax = -1;
     for (int i = 0; i < count; ++i) {
         const rlbm_problem& p = probs[i];
+        if (special_bc(p.bc_x, p.bc_y)) {   // the batch kernels carry no boundary loads
+            rlbm_batch_destroy(b);
+            return RLBM_EINVAL;
+        }
         rlbm_ctx c = nullptr;
         int rc = rlbm_init_quadrature(&c, p.n_radial, p.n_angle, p.order, p.rotate);
         if (rc == RLBM_OK) {

@@ -24,13 +24,14 @@ size_t elem_size(int prec) { return prec == RLBM_F64 ? 8 : (prec == RLBM_F32 ? 4
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t f0, f1, fields, partials, flag, pp0, pp1, total;
+    size_t f0, f1, fields, partials, flag, edges, pp0, pp1, total;
 };
 
 // Workspace: two population buffers, the field outputs, the per-block
-// partial charges, the non-physical flag and the push kernel's two
-// partial-sum buffers (present whichever kernel is chosen, so that neither
-// rlbm_step nor rlbm_set_kernel allocates).
+// partial charges, the non-physical flag, the initial populations of the
+// edge cells (FIXED boundaries) and the push kernel's two partial-sum
+// buffers (present whichever kernel is chosen, so that neither rlbm_step nor
+// rlbm_set_kernel allocates).
 Layout layout(int nvel, int nx, int ny, int prec)
 {
     const long long S = (long long)nx * ny;
@@ -43,7 +44,8 @@ Layout layout(int nvel, int nx, int ny, int prec)
     L.fields = L.f1 + fb;
     L.partials = L.fields + align256((size_t)4 * S * sizeof(double));
     L.flag = L.partials + align256((size_t)fields_blocks(S) * 4 * sizeof(double));
-    L.pp0 = L.flag + 256;
+    L.edges = L.flag + 256;
+    L.pp0 = L.edges + align256((size_t)2 * (nx + ny) * nvel * elem_size(prec));
     L.pp1 = L.pp0 + pb;
     L.total = L.pp1 + pb;
     return L;
@@ -81,8 +83,12 @@ int upload_tables_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, long long
         for (int j = 0; j < (int)(sizeof(A.P) / sizeof(T)); ++j) A.P[j] = (T)R.P[j];
         for (int t = 0; t < 2 * NM + 1; ++t) B.H[t] = (T)R.H[t];
         B.cth = (T)R.cth; B.sth = (T)R.sth;
-        sg[v] = (unsigned char)((R.sx > 0 ? 0 : 1) | (R.sy > 0 ? 0 : 2));
+        // bit 2: the reversed velocity (theta + pi, same shell) is K/2
+        // planes below; null entries read the last plane (angle K - 1), so
+        // they carry it too (set below)
+        sg[v] = (unsigned char)((R.sx > 0 ? 0 : 1) | (R.sy > 0 ? 0 : 2) | (v % c->q.K >= (size_t)c->q.K / 2 ? 4 : 0));
     }
+    for (size_t v = nv; v < npad; ++v) sg[v] = 4;
     hipError_t e;
     if ((e = hipMalloc(&c->d_srec, npad * sizeof(SRec<T>))) != hipSuccess) return fail(c, RLBM_ENOMEM, "table alloc");
     if ((e = hipMalloc(&c->d_crec, npad * sizeof(CRec<T, NM>))) != hipSuccess) return fail(c, RLBM_ENOMEM, "table alloc");
@@ -122,10 +128,12 @@ bool finite_arr(const double* a, long long S)
 }  // namespace
 
 // Automatic choice: the push kernel where a tile's streamed values would not
-// fit the register budget of the tile kernel (large velocity sets).
+// fit the register budget of the tile kernel (large velocity sets), unless a
+// WALL or FIXED axis needs the tile kernel's boundary loads.
 int resolve_kernel(rlbm_ctx c)
 {
     if (c->kern != RLBM_KERNEL_AUTO) return c->kern;
+    if (special_bc(c->bcx, c->bcy)) return RLBM_KERNEL_TILE;
     return c->q.nvel >= RLBM_PUSH_MIN_NVEL ? RLBM_KERNEL_PUSH : RLBM_KERNEL_TILE;
 }
 
@@ -136,6 +144,7 @@ SCParams make_params(rlbm_ctx c, int waves)
     p.srec = c->d_srec;
     p.crec = c->d_crec;
     p.sgn = c->d_sgn;
+    p.edges = c->d_edges;
     p.G = c->d_G;
     p.Pc = c->d_Pc;
     p.nx = c->nx; p.ny = c->ny; p.nvel = c->q.nvel; p.K = c->q.K; p.Np = c->q.Np; p.N = c->q.N;
@@ -194,8 +203,10 @@ int rlbm_init_fields(rlbm_ctx c, int nx, int ny, const double* n, const double* 
     if (!n || !T) return fail(c, RLBM_EINVAL, "n and T are required");
     if (!(tau > 0.0) || std::isnan(tau)) return fail(c, RLBM_EINVAL, "tau must be > 0 (inf allowed)");
     if (!(dt > 0.0 && dt <= 1.0)) return fail(c, RLBM_EINVAL, "dt must be in (0, 1]");
-    if ((bc_x != RLBM_BC_PERIODIC && bc_x != RLBM_BC_CLAMP) || (bc_y != RLBM_BC_PERIODIC && bc_y != RLBM_BC_CLAMP))
+    if (bc_x < RLBM_BC_PERIODIC || bc_x > RLBM_BC_FIXED || bc_y < RLBM_BC_PERIODIC || bc_y > RLBM_BC_FIXED)
         return fail(c, RLBM_EINVAL, "bad boundary condition");
+    if ((bc_x == RLBM_BC_WALL || bc_y == RLBM_BC_WALL) && (c->q.K % 2))
+        return fail(c, RLBM_EINVAL, "a wall needs an even number of angles (reversed velocities)");
     if (precision != RLBM_F64 && precision != RLBM_F32) return fail(c, RLBM_EINVAL, "unsupported precision");
     if (d_workspace && ((uintptr_t)d_workspace & 255)) return fail(c, RLBM_EINVAL, "workspace must be 256-byte aligned");
     const long long S = (long long)nx * ny;
@@ -246,6 +257,7 @@ int rlbm_init_fields(rlbm_ctx c, int nx, int ny, const double* n, const double* 
     c->d_fields = reinterpret_cast<double*>(c->ws + L.fields);
     c->d_partials = reinterpret_cast<double*>(c->ws + L.partials);
     c->d_flag = reinterpret_cast<int*>(c->ws + L.flag);
+    c->d_edges = c->ws + L.edges;
     c->pp[0] = c->ws + L.pp0;
     c->pp[1] = c->ws + L.pp1;
     c->cur = 0;
@@ -295,6 +307,8 @@ int rlbm_init_fields(rlbm_ctx c, int nx, int ny, const double* n, const double* 
     e = launch_init(precision, nmax_of(c->q.N), c->d_fields, c->f[0], c->d_veld, c->d_G, c->d_Pc, nx, ny,
                     c->q.nvel, c->q.K, c->q.Np, st);
     if (e != hipSuccess) return hip_fail(c, e, "init kernel");
+    e = launch_edges(precision, c->f[0], c->d_edges, nx, ny, c->q.nvel, st);
+    if (e != hipSuccess) return hip_fail(c, e, "edge copy kernel");
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(c, e, "init sync");
     if (!c->ev0) {
         if ((e = hipEventCreate(&c->ev0)) != hipSuccess) return hip_fail(c, e, "event");
@@ -325,6 +339,7 @@ int rlbm_step(rlbm_ctx c, int nsteps)
     if (!c->have_fields) return fail(c, RLBM_ESTATE, "rlbm_step before rlbm_init_fields");
     if (nsteps < 0) return fail(c, RLBM_EINVAL, "nsteps < 0");
     if (resolve_kernel(c) == RLBM_KERNEL_PUSH) {
+        if (special_bc(c->bcx, c->bcy)) return fail(c, RLBM_EINVAL, "walls and fixed edges need the tile kernel");
         if (!c->d_prec) return fail(c, RLBM_ESTATE, "push kernel tables missing");
         hipError_t e;
         if (!c->pvalid && nsteps > 0) {
@@ -469,6 +484,8 @@ int rlbm_set_kernel(rlbm_ctx c, int kind)
     if (!c) return RLBM_EINVAL;
     if (kind != RLBM_KERNEL_AUTO && kind != RLBM_KERNEL_TILE && kind != RLBM_KERNEL_PUSH)
         return fail(c, RLBM_EINVAL, "unknown kernel kind");
+    if (kind == RLBM_KERNEL_PUSH && c->have_fields && special_bc(c->bcx, c->bcy))
+        return fail(c, RLBM_EINVAL, "walls and fixed edges need the tile kernel");
     c->kern = kind;
     c->pvalid = 0;
     return RLBM_OK;

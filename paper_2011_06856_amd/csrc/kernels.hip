@@ -71,7 +71,7 @@ __device__ __forceinline__ int wrap_idx(int i, int n, int bc)
 // block a few tiles wide and P.band tall, so that the upwind row a tile reads
 // is read by its neighbour in the block at about the same time (L2 reuse even
 // when one grid row of all velocities exceeds the L2).
-template <typename TS, typename TC, int NM, int VPT>
+template <typename TS, typename TC, int NM, int VPT, bool BC = false>
 __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restrict__ fout,
                                         const SRec<TC>* srec_, const CRec<TC, NM>* crec_, const double* Gtab_,
                                         const double* Pc_, const SCParams& P, int tile, unsigned char* smem)
@@ -110,7 +110,10 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
     // Interior tiles (all 64 columns and both x neighbours inside the grid)
     // reach the x neighbour by a scalar shift of the row base; edge tiles
     // select a wrapped or clamped column per lane.
-    const bool interior = tx > 0 && (tx + 1) * 64 < P.nx;
+    // WALL and FIXED axes: upwind points outside the grid take the boundary's
+    // values (the rows next to such an edge are edge tiles too)
+    const bool bxs = BC && P.bcx >= RLBM_BC_WALL, bys = BC && P.bcy >= RLBM_BC_WALL;
+    const bool interior = tx > 0 && (tx + 1) * 64 < P.nx && !(bys && (ty == 0 || ty == P.ny - 1));
     constexpr unsigned ES = sizeof(TS);
     const unsigned ocb = (unsigned)xc * ES;
     const unsigned omb = (unsigned)wrap_idx(xc - 1, P.nx, P.bcx) * ES;
@@ -135,23 +138,43 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
         rcur += pbytes;
         return p;
     };
-    // upwind signs from the sign bits of the moment rows p c and p s
-    auto xneg = [](TC pc) __attribute__((always_inline)) -> bool {
-        return (__builtin_bit_cast(std::conditional_t<sizeof(TC) == 8, unsigned long long, unsigned>, pc) >>
-                (sizeof(TC) * 8 - 1)) != 0;
-    };
-
     auto ld = [](const char* base, unsigned off) __attribute__((always_inline)) -> TC { return (TC)*reinterpret_cast<const TS*>(base + off); };
-    // code: bit 0 upwind column x + 1, bit 1 upwind row y + 1
-    auto load4 = [&](auto fast, unsigned code, const char* p0, TC* r) __attribute__((always_inline)) {
-        const bool cneg = code & 1;
-        const char* p1 = p0 + ((code & 2) ? dpb : dmb);
+    // boundary values: the reversed velocity's plane (K/2 planes away) and
+    // the initial populations of the edge cells
+    const long long rev = (long long)(P.K / 2) * pbytes;
+    const char* const edges = reinterpret_cast<const char*>(P.edges);
+    auto edge_x = [&](int side, int v, int row) __attribute__((always_inline)) -> TC {
+        return *reinterpret_cast<const TS*>(edges + (((long long)side * P.nvel + min(v, P.nvel - 1)) * P.ny + row) * ES);
+    };
+    auto edge_y = [&](int side, int v, int col) __attribute__((always_inline)) -> TC {
+        return *reinterpret_cast<const TS*>(
+            edges + ((2LL * P.nvel * P.ny) + ((long long)side * P.nvel + min(v, P.nvel - 1)) * P.nx + col) * ES);
+    };
+    // code: bit 0 upwind column x + 1, bit 1 upwind row y + 1, bit 2 the
+    // reversed velocity K/2 planes below
+    auto load4 = [&](auto fast, int v, unsigned code, const char* p0, TC* r) __attribute__((always_inline)) {
+        const bool cneg = code & 1, sneg = code & 2;
+        const char* p1 = p0 + (sneg ? dpb : dmb);
         if (decltype(fast)::value) {
             const int dx = cneg ? (int)ES : -(int)ES;
             r[0] = ld(p0, ocb); r[1] = ld(p0 + dx, ocb); r[2] = ld(p1, ocb); r[3] = ld(p1 + dx, ocb);
         } else {
             const unsigned osb = cneg ? opb : omb;
             r[0] = ld(p0, ocb); r[1] = ld(p0, osb); r[2] = ld(p1, ocb); r[3] = ld(p1, osb);
+            if (BC && (bxs || bys)) {
+                const bool xo = bxs && (cneg ? xc + 1 >= P.nx : xc == 0);   // this lane's upwind column is outside
+                const bool yo = bys && (sneg ? ty + 1 >= P.ny : ty == 0);   // the upwind row is outside
+                if (xo || yo) {
+                    const bool xw = xo && P.bcx == RLBM_BC_WALL, yw = yo && P.bcy == RLBM_BC_WALL;
+                    TC back = TC(0);
+                    if (xw || yw) back = ld(p0 + ((code & 4) ? -rev : rev), ocb);
+                    const int sxi = cneg ? 1 : 0, syi = sneg ? 1 : 0;
+                    const int ysrc = wrap_idx(sneg ? ty + 1 : ty - 1, P.ny, P.bcy);
+                    if (xo) r[1] = xw ? back : edge_x(sxi, v, ty);
+                    if (yo) r[2] = yw ? back : edge_y(syi, v, xc);
+                    r[3] = (xw || yw) ? back : (xo ? edge_x(sxi, v, ysrc) : edge_y(syi, v, (int)(osb / ES)));
+                }
+            }
         }
     };
     auto bilin = [&](int v, const TC* r) __attribute__((always_inline)) -> TC {
@@ -179,7 +202,7 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
                     *(const RLBM_CONST_AS unsigned long long*)((const RLBM_CONST_AS unsigned char*)P.sgn + v0 + kb * LB);
 #pragma unroll
                 for (int b = 0; b < LB; ++b)
-                    load4(fast, (unsigned)(sg >> (8 * b)) & 3u, rnext(v0 + kb * LB + b), raw[b]);
+                    load4(fast, v0 + kb * LB + b, (unsigned)(sg >> (8 * b)) & 7u, rnext(v0 + kb * LB + b), raw[b]);
                 // FP32: each batch's 8-term sums start from zero and are
                 // carried into FP64 accumulators (FP32 rounds only within
                 // a batch); FP64 accumulates directly
@@ -206,7 +229,7 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
         }
         for (int v = v0 + VPT; v < v0 + P.chunk; ++v) {
             TC r[4];
-            load4(fast, (xneg(srec[v].P[1]) ? 1u : 0u) | (xneg(srec[v].P[2]) ? 2u : 0u), inb + rplane(v), r);
+            load4(fast, v, ((const RLBM_CONST_AS unsigned char*)P.sgn)[v], inb + rplane(v), r);
             const TC f = bilin(v, r);
             CSRec& R = srec[v];
 #pragma unroll
@@ -299,7 +322,7 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
         }
         for (int v = v0 + VPT; v < v0 + P.chunk; ++v) {
             TC r[4];
-            load4(fast, (xneg(srec[v].P[1]) ? 1u : 0u) | (xneg(srec[v].P[2]) ? 2u : 0u), inb + rplane(v), r);
+            load4(fast, v, ((const RLBM_CONST_AS unsigned char*)P.sgn)[v], inb + rplane(v), r);
             collide(fast, v, outb + wplane(v), bilin(v, r));
         }
     };
@@ -309,7 +332,9 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
         phase4(std::false_type{});
 }
 
-template <typename TS, typename TC, int NM, int VPT>
+// BC: the instance with the boundary loads of WALL and FIXED axes (a
+// separate instance, so that the others keep their register budget).
+template <typename TS, typename TC, int NM, int VPT, bool BC>
 __global__ __launch_bounds__(1024) void k_stream_collide(const TS* __restrict__ fin, TS* __restrict__ fout,
                                                          const SRec<TC>* __restrict__ srec,
                                                          const CRec<TC, NM>* __restrict__ crec,
@@ -317,7 +342,7 @@ __global__ __launch_bounds__(1024) void k_stream_collide(const TS* __restrict__ 
                                                          const double* __restrict__ Pc, SCParams P)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    sc_tile<TS, TC, NM, VPT>(fin, fout, srec, crec, Gtab, Pc, P, xcd_remap(blockIdx.x, gridDim.x), smem);
+    sc_tile<TS, TC, NM, VPT, BC>(fin, fout, srec, crec, Gtab, Pc, P, xcd_remap(blockIdx.x, gridDim.x), smem);
 }
 
 // Batched form: many independent problems advance one step in one
@@ -458,8 +483,8 @@ __global__ __launch_bounds__(256) void k_fields(const TS* __restrict__ f, const 
     if (threadIdx.x < 4) partials[(size_t)blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-template <typename TS, typename TC, int NM, int VPT>
-hipError_t launch_sc_t(int waves, const SCParams& p, hipStream_t st)
+template <typename TS, typename TC, int NM, int VPT, bool BC>
+hipError_t launch_sc_b(int waves, const SCParams& p, hipStream_t st)
 {
     constexpr int NT = 2 * NM + 1;
     constexpr int NMOM = sizeof(TC) == 8 ? 9 : 8;
@@ -467,17 +492,24 @@ hipError_t launch_sc_t(int waves, const SCParams& p, hipStream_t st)
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     static size_t configured = 0;
     if (lds > 64 * 1024 && lds > configured) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stream_collide<TS, TC, NM, VPT>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stream_collide<TS, TC, NM, VPT, BC>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         configured = lds;
     }
     const long long tiles = (long long)((p.nx + 63) / 64) * p.ny;
     if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_stream_collide<TS, TC, NM, VPT>), dim3((unsigned)tiles), dim3(64 * waves), lds, st,
+    hipLaunchKernelGGL((k_stream_collide<TS, TC, NM, VPT, BC>), dim3((unsigned)tiles), dim3(64 * waves), lds, st,
                        static_cast<const TS*>(p.fin), static_cast<TS*>(p.fout),
                        static_cast<const SRec<TC>*>(p.srec), static_cast<const CRec<TC, NM>*>(p.crec), p.G, p.Pc, p);
     return hipGetLastError();
+}
+
+template <typename TS, typename TC, int NM, int VPT>
+hipError_t launch_sc_t(int waves, const SCParams& p, hipStream_t st)
+{
+    if (special_bc(p.bcx, p.bcy)) return launch_sc_b<TS, TC, NM, VPT, true>(waves, p, st);
+    return launch_sc_b<TS, TC, NM, VPT, false>(waves, p, st);
 }
 
 // Held values per lane, by storage precision and order class: the register
@@ -653,6 +685,44 @@ int batch_grid(int prec, int nmax, int waves, int max_np)
 hipError_t launch_reset_counters(int* counters, hipStream_t st)
 {
     hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, st, counters);
+    return hipGetLastError();
+}
+
+namespace {
+// Initial populations of the edge cells, for FIXED boundaries:
+// E[side][v][y] = f[v][y][side ? nx-1 : 0], then E[side][v][x] = f[v][side ? ny-1 : 0][x].
+template <typename TS>
+__global__ __launch_bounds__(256) void k_edges(const TS* __restrict__ f, TS* __restrict__ E, int nx, int ny, int nvel)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nxe = 2LL * nvel * ny, total = nxe + 2LL * nvel * nx;
+    if (i >= total) return;
+    const long long S = (long long)nx * ny;
+    if (i < nxe) {
+        const int y = (int)(i % ny);
+        const long long sv = i / ny;
+        const int v = (int)(sv % nvel), side = (int)(sv / nvel);
+        E[i] = f[(long long)v * S + (long long)y * nx + (side ? nx - 1 : 0)];
+    } else {
+        const long long j = i - nxe;
+        const int x = (int)(j % nx);
+        const long long sv = j / nx;
+        const int v = (int)(sv % nvel), side = (int)(sv / nvel);
+        E[i] = f[(long long)v * S + (long long)(side ? ny - 1 : 0) * nx + x];
+    }
+}
+}  // namespace
+
+hipError_t launch_edges(int prec, const void* f, void* edges, int nx, int ny, int nvel, hipStream_t st)
+{
+    const long long total = 2LL * nvel * (nx + ny);
+    const unsigned blocks = (unsigned)((total + 255) / 256);
+    if (prec == RLBM_F64)
+        hipLaunchKernelGGL((k_edges<double>), dim3(blocks), dim3(256), 0, st, (const double*)f, (double*)edges, nx, ny, nvel);
+    else if (prec == RLBM_F32)
+        hipLaunchKernelGGL((k_edges<float>), dim3(blocks), dim3(256), 0, st, (const float*)f, (float*)edges, nx, ny, nvel);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

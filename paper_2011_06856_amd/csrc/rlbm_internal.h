@@ -189,7 +189,10 @@ struct SCParams {
     void* fout;
     const void* srec;      // SRec<TC>[nvel + RLBM_VPAD]
     const void* crec;      // CRec<TC, NM>[nvel + RLBM_VPAD]
-    const unsigned char* sgn;   // [nvel + RLBM_VPAD]: bit 0 cos < 0, bit 1 sin < 0 (upwind x + 1, y + 1)
+    const unsigned char* sgn;   // [nvel + RLBM_VPAD]: bit 0 cos < 0, bit 1 sin < 0 (upwind x + 1, y + 1),
+                                // bit 2 the reversed velocity lies K/2 planes below (else above)
+    const void* edges;     // initial populations of the edge cells (FIXED axes):
+                           // [2][nvel][ny] (columns 0, nx-1) then [2][nvel][nx] (rows 0, ny-1)
     const double* G;       // [Np][NMAX+1][NMAX+1]
     const double* Pc;
     int nx, ny, nvel, K, Np, N;
@@ -237,6 +240,7 @@ struct rlbm_ctx_s {
     int cur = 0;
     double* d_fields = nullptr;
     double* d_partials = nullptr;
+    void* d_edges = nullptr;             // SCParams::edges (in the workspace)
     int* d_flag = nullptr;
     void* d_srec = nullptr;              // SRec<TC>[nvel + RLBM_VPAD]
     void* d_crec = nullptr;              // CRec<TC, NM>[nvel + RLBM_VPAD]
@@ -263,7 +267,12 @@ struct rlbm_ctx_s {
 inline int nmax_of(int N) { return N <= 3 ? 3 : (N <= 5 ? 5 : 7); }
 SCParams make_params(rlbm_ctx c, int waves);   // capi.cpp
 
+// A WALL or FIXED axis: upwind points outside the grid need the tile
+// kernel's boundary loads.
+inline bool special_bc(int bcx, int bcy) { return bcx >= RLBM_BC_WALL || bcy >= RLBM_BC_WALL; }
+
 // Launchers (kernels.hip).
+hipError_t launch_edges(int prec, const void* f, void* edges, int nx, int ny, int nvel, hipStream_t st);
 hipError_t launch_init(int prec, int nmax, const double* fields, void* f, const VelRec<double>* vel, const double* G,
                        const double* Pc, int nx, int ny, int nvel, int K, int Np, hipStream_t st);
 hipError_t launch_stream_collide(int prec, int nmax, int waves, const SCParams& p, hipStream_t st);

@@ -73,9 +73,20 @@ def feq_moments_numeric(mons, n, T, U, M=128):
 
 
 class Lattice:
-    def __init__(self, Np, K, N, nx, ny, fields, tau, dt, dps=40):
+    """bc = (bc_x, bc_y), each 'periodic', 'wall' (a source across the edge
+    is replaced by the target cell's population of the opposite velocity) or
+    'fixed' (a source across the edge keeps the initial population of the
+    nearest cell)."""
+
+    def __init__(self, Np, K, N, nx, ny, fields, tau, dt, dps=40, bc=("periodic", "periodic")):
         mp.mp.dps = dps
+        self.bc = bc
         self.vel = quadrature(Np, K)
+        # opposite velocity: same shell, (cos, sin) -> (-cos, -sin), found by search
+        self.opp = []
+        for (p, ct, st, w) in self.vel:
+            self.opp.append(min(range(len(self.vel)), key=lambda u: abs(self.vel[u][0] - p)
+                                + abs(self.vel[u][1] + ct) + abs(self.vel[u][2] + st)))
         self.mons, self.G = _gram(N)
         self.nx, self.ny, self.tau, self.dt = nx, ny, mp.mpf(tau), mp.mpf(dt)
         n, T, ux, uy = fields
@@ -86,6 +97,22 @@ class Lattice:
                 fe = self.feq(mp.mpf(n[y][x]), mp.mpf(T[y][x]), U)
                 for v in range(len(self.vel)):
                     self.f[(v, y, x)] = fe[v]
+        self.f0 = dict(self.f)
+
+    def _source(self, v, y, x, ys, xs):
+        """Population of velocity v at the upwind point (xs, ys) of target (x, y)."""
+        outside = []
+        for axis, (i, n) in enumerate(((xs, self.nx), (ys, self.ny))):
+            if self.bc[axis] == "periodic":
+                continue
+            if not 0 <= i < n:
+                outside.append(self.bc[axis])
+        xs, ys = xs % self.nx if self.bc[0] == "periodic" else xs, ys % self.ny if self.bc[1] == "periodic" else ys
+        if "wall" in outside:
+            return self.f[(self.opp[v], y, x)]
+        if outside:
+            return self.f0[(v, min(max(ys, 0), self.ny - 1), min(max(xs, 0), self.nx - 1))]
+        return self.f[(v, ys, xs)]
 
     @staticmethod
     def _U(ux, uy):
@@ -136,9 +163,9 @@ class Lattice:
             sy = 1 if st >= 0 else -1
             for y in range(ny):
                 for x in range(nx):
-                    x1, y1 = (x - sx) % nx, (y - sy) % ny
-                    fs[(v, y, x)] = ((1 - ax) * (1 - ay) * self.f[(v, y, x)] + ax * (1 - ay) * self.f[(v, y, x1)]
-                                     + (1 - ax) * ay * self.f[(v, y1, x)] + ax * ay * self.f[(v, y1, x1)])
+                    src = lambda ys, xs: self._source(v, y, x, ys, xs)
+                    fs[(v, y, x)] = ((1 - ax) * (1 - ay) * self.f[(v, y, x)] + ax * (1 - ay) * src(y, x - sx)
+                                     + (1 - ax) * ay * src(y - sy, x) + ax * ay * src(y - sy, x - sx))
         nv = len(self.vel)
         for y in range(ny):
             for x in range(nx):

@@ -105,6 +105,12 @@ def test_invalid_arguments_are_rejected_without_a_device():
     assert init(n, T, tau=math.nan) == R.RLBM_EINVAL
     assert init(n, T, dt=1.5) == R.RLBM_EINVAL
     assert init(n, T, bc=7) == R.RLBM_EINVAL
+    h7 = ctypes.c_void_p()
+    assert L.rlbm_init_quadrature(ctypes.byref(h7), 3, 7, 2, 1) == R.RLBM_OK
+    assert L.rlbm_init_fields(h7, nx, ny, R._p(n), R._p(T), None, None, 1.0, 1.0, 2, 0, 1, None, None) == \
+        R.RLBM_EINVAL                                                       # wall with an odd angle count
+    assert b"even" in L.rlbm_last_error(h7)
+    assert L.rlbm_destroy(h7) == R.RLBM_OK
     assert init(n, T, prec=9) == R.RLBM_EINVAL
     assert L.rlbm_step(h, 1) == R.RLBM_ESTATE
     assert b"before" in L.rlbm_last_error(h)
