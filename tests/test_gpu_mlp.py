@@ -309,28 +309,33 @@ def test_readout_matches_oracle_forward():
         rl.MLP(max_batch=nx * ny).readout(s, extra)   # three outputs: not a readout network
 
 
-def test_trained_readout_reduces_the_coarse_error():
-    """What the trained network gains: a readout network trained (by the
-    library's forward, backward and Adam kernels) on coarse/fine pairs of
-    random shocks lowers the error of the coarse fields against the fine run.
-    Reduced protocol: 256^2, K 24 against 192, 0.9 t_max, 40 seeds with 16384
-    sampled sites each; the error is taken over all sites of 8 of those runs.
-    On held-out seeds the gain needs the benchmark's full protocol (200
-    seeds, 40960 sites each, 512^2, K 24 against 384): there the error of
-    beta falls by 22%, of eps by 17% and of n by 11% (bench --form learned)."""
+@pytest.mark.slow
+def test_trained_readout_gains_on_held_out_seeds():
+    """What the trained network gains over the method without it, on runs it
+    never saw: the readout network is trained (by the library's forward,
+    backward and Adam kernels) on the learned form's full protocol (512^2,
+    K = 24 against K = 384, 0.9 t_max, training seeds 0..199 with 40960
+    sampled sites each, 15 epochs) and evaluated on the 20 held-out seeds
+    10000..10019.  The mean error (Eq. rel_err per field) of the corrected
+    coarse fields against the fine run must be at least 5% below that of the
+    plain coarse run in every field.  Smaller protocols (256^2 with 200 or
+    400 seeds) gain nothing on held-out seeds (ratios 0.97 to 1.11): the
+    correction needs this many configurations to generalise."""
     rl = _rl()
     from paper_2011_06856_amd import learned as Lr
-    side, Kc, Kf, steps = 256, 24, 192, int(0.45 * 256)
-    X, T = Lr.collect_readout(side, range(40), Kc, Kf, steps, rows=16384)
+    side, Kc, Kf, steps = 512, 24, 384, 230
+    X, T = Lr.collect_readout(side, range(200), Kc, Kf, steps, rows=40960,
+                              log=lambda m: say(m))
     nm = Lr.Normaliser(X, T)
     net = rl.MLP(max_batch=side * side, out_dim=4)
     net.init_params(seed=1)
     nm.apply(net)
     losses = Lr.train(net, nm.inputs(X), nm.targets(T), epochs=15, batch=4096, lr=1e-3)
-    res = Lr.evaluate_readout(net, side, range(8), Kc, Kf, steps)
+    del X, T
+    res = Lr.evaluate_readout(net, side, range(10000, 10020), Kc, Kf, steps)
     plain = {k: float(np.mean([r["plain"][k] for r in res])) for k in ("n", "eps", "beta")}
     corr = {k: float(np.mean([r["corrected"][k] for r in res])) for k in ("n", "eps", "beta")}
-    say("readout training loss %.3f -> %.3f; plain %s corrected %s" % (losses[0], losses[-1], plain, corr))
+    say("held-out readout: loss %.3f -> %.3f; plain %s corrected %s" % (losses[0], losses[-1], plain, corr))
     assert losses[-1] < 0.9 * losses[0]
-    assert corr["beta"] < 0.9 * plain["beta"]
-    assert corr["eps"] < plain["eps"]
+    for k in ("n", "eps", "beta"):
+        assert corr[k] < 0.95 * plain[k], (k, corr[k], plain[k])

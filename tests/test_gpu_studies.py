@@ -5,6 +5,7 @@ falling with the population count in the near-ballistic one (Kn = 10), the
 behaviour Sec. 3.1 reports for its Fig. 3."""
 import sys
 
+import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -23,3 +24,20 @@ def test_tube_error_depends_on_angles_only_beyond_hydro():
     assert lo[1] < 1.2 * lo[2]                               # Kn 0.05: saturated by N_pop ~ 100
     assert res[0.05]["saturation_npop"] <= 96
     assert hi[0] > hi[1] > 2 * hi[2]                         # Kn 10: still falling beyond 96
+
+
+def test_tube_study_numbers_match_the_oracle():
+    """The study's error numbers on the GPU path equal those of the same runs
+    on the FP64 oracle (the runs agree to rounding, so the errors do too)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2011_06856_amd import studies
+    from test_oracle_studies import oracle_tube_errors
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    Ks = (8, 24, 96)
+    res = studies.tube_study(Kns=(0.05, 10.0), Ks=Ks, L=200, refine=2, K_ref=120, log=log)
+    for Kn in (0.05, 10.0):
+        ref = oracle_tube_errors(200, 2, 120, Ks, Kn)
+        log("Kn %g: GPU %s oracle %s" % (Kn, res[Kn]["eps"], ref))
+        np.testing.assert_allclose(res[Kn]["eps"], ref, rtol=1e-9)
