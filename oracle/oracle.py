@@ -49,7 +49,11 @@ def _lib():
         L.orc_landau.argtypes = [_dp, _dp]
         L.orc_sim_new.restype = ctypes.c_void_p
         L.orc_sim_new.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp,
-                                  ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int]
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.orc_feq_qs.argtypes = [ctypes.c_void_p] + [ctypes.c_double] * 4 + [ctypes.c_int, _dp]
+        L.orc_qs_G.restype = ctypes.c_double
+        L.orc_qs_G.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int]
+        L.orc_qs_landau.argtypes = [_dp, ctypes.c_int, _dp]
         L.orc_sim_free.argtypes = [ctypes.c_void_p]
         L.orc_sim_step.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.orc_sim_stream.argtypes = [ctypes.c_void_p, ctypes.c_int]
@@ -110,10 +114,15 @@ class Quadrature:
         _lib().orc_quad_basis(self._h, _ptr(J), ex.ctypes.data_as(_ip))
         return J, ex
 
-    def feq(self, n, T, ux=0.0, uy=0.0):
-        """Discrete truncated equilibrium f_eq_v (Eq. mj-feq-expansion-truncated)."""
+    def feq(self, n, T, ux=0.0, uy=0.0, stat=0):
+        """Discrete truncated equilibrium f_eq_v (Eq. mj-feq-expansion-truncated)
+        of the statistics stat (0 Maxwell-Juttner, 1 Fermi-Dirac, 2
+        Bose-Einstein; Eq. feq_dist)."""
         out = np.zeros(self.nvel)
-        _lib().orc_feq(self._h, n, T, ux, uy, _ptr(out))
+        if stat == 0:
+            _lib().orc_feq(self._h, n, T, ux, uy, _ptr(out))
+        elif _lib().orc_feq_qs(self._h, n, T, ux, uy, int(stat), _ptr(out)):
+            raise ValueError("no equilibrium of statistics %d at n=%g, T=%g" % (stat, n, T))
         return out
 
     def eq_coeffs(self, n, T, ux=0.0, uy=0.0):
@@ -143,6 +152,22 @@ def landau(mom):
     return out, bad == 0
 
 
+STATISTICS = {"mj": 0, "fd": 1, "be": 2}
+
+
+def qs_G(k, z, stat):
+    """Radial integral G_k(z) of the statistics (z, -Li_{k+1}(-z), Li_{k+1}(z))."""
+    return _lib().orc_qs_G(int(k), float(z), int(stat))
+
+
+def qs_landau(mom, stat):
+    """Landau frame and statistics -> (n, eps, U^x, U^y, T, U^0, z, phi_2), ok."""
+    m = np.ascontiguousarray(mom, dtype=np.float64)
+    out = np.zeros(8)
+    bad = _lib().orc_qs_landau(_ptr(m), int(stat), _ptr(out))
+    return out, bad == 0
+
+
 def site_stats(mom):
     """(n, eps, U^x, U^y, pi^xx, pi^xy, pi^yy) of one site from its nine
     moments: Landau frame, then the shear stress of the Landau-Lifshitz
@@ -163,14 +188,14 @@ class Sim:
     four-velocity.  bc: 0 periodic, 1 clamp (zero gradient), per axis.
     """
 
-    def __init__(self, quad, nx, ny, n, T, ux=None, uy=None, tau=np.inf, dt=1.0, bcx=0, bcy=0):
+    def __init__(self, quad, nx, ny, n, T, ux=None, uy=None, tau=np.inf, dt=1.0, bcx=0, bcy=0, stat=0):
         self.q, self.nx, self.ny = quad, nx, ny
         S = nx * ny
         fld = [np.ascontiguousarray(np.broadcast_to(a, (ny, nx)), dtype=np.float64).reshape(S)
                for a in (n, T, 0.0 if ux is None else ux, 0.0 if uy is None else uy)]
         self._keep = fld
         self._h = _lib().orc_sim_new(quad._h, nx, ny, *[_ptr(a) for a in fld],
-                                     float(tau), float(dt), int(bcx), int(bcy))
+                                     float(tau), float(dt), int(bcx), int(bcy), int(stat))
         if not self._h:
             raise ValueError("invalid simulation arguments")
 

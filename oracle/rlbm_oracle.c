@@ -304,7 +304,7 @@ double orc_mj_moment(int k, const int* idx, double n, double T, double ux, doubl
 
 /* Expansion coefficients a_b = int f_eq J_b d^2p/p^0 (Eq.
  * mj-projection-coefficients), each J_b being a combination of monomials. */
-static void eq_coeffs(const orc_quad* q, ld n, ld T, const ld* U, ld* a)
+static void eq_coeffs(const orc_quad* q, ld n, ld T, const ld* U, const ld* phi, ld* a)
 {
     int nb = q->nb;
     ld mu[81];
@@ -313,7 +313,9 @@ static void eq_coeffs(const orc_quad* q, ld n, ld T, const ld* U, ld* a)
         for (int t = 0; t < q->ea[s]; ++t) idx[k++] = 0;
         for (int t = 0; t < q->eb[s]; ++t) idx[k++] = 1;
         for (int t = 0; t < q->ec[s]; ++t) idx[k++] = 2;
-        mu[s] = mj_moment(idx, k, n, T, U);
+        /* Fermi-Dirac / Bose-Einstein: the rank-k moment is the
+         * Maxwell-Juttner one scaled by phi[k] (see qs_G below) */
+        mu[s] = mj_moment(idx, k, n, T, U) * (phi ? phi[k] : 1.0L);
     }
     for (int b = 0; b < nb; ++b) {
         ld acc = 0.0L;
@@ -324,10 +326,10 @@ static void eq_coeffs(const orc_quad* q, ld n, ld T, const ld* U, ld* a)
 
 /* Discrete truncated equilibrium f_eq_v = w_v sum_b a_b J_b(p_v)
  * (Eq. mj-feq-expansion-truncated).  The truncation is not clamped. */
-static void feq_site(const orc_quad* q, ld n, ld T, const ld* U, double* feq)
+static void feq_site(const orc_quad* q, ld n, ld T, const ld* U, const ld* phi, double* feq)
 {
     ld a[81];
-    eq_coeffs(q, n, T, U, a);
+    eq_coeffs(q, n, T, U, phi, a);
     for (int v = 0; v < q->nvel; ++v) {
         ld acc = 0.0L;
         for (int b = 0; b < q->nb; ++b) acc += a[b] * (ld)q->J[(size_t)b * q->nvel + v];
@@ -338,15 +340,218 @@ static void feq_site(const orc_quad* q, ld n, ld T, const ld* U, double* feq)
 void orc_feq(const orc_quad* q, double n, double T, double ux, double uy, double* feq)
 {
     ld U[3] = {sqrtl(1.0L + (ld)ux * ux + (ld)uy * uy), ux, uy};
-    feq_site(q, n, T, U, feq);
+    feq_site(q, n, T, U, NULL, feq);
 }
 
 void orc_eq_coeffs(const orc_quad* q, double n, double T, double ux, double uy, double* a)
 {
     ld U[3] = {sqrtl(1.0L + (ld)ux * ux + (ld)uy * uy), ux, uy};
     ld al[81];
-    eq_coeffs(q, n, T, U, al);
+    eq_coeffs(q, n, T, U, NULL, al);
     for (int b = 0; b < q->nb; ++b) a[b] = (double)al[b];
+}
+
+/* ------------------------------------------------------------------------- */
+/* Fermi-Dirac and Bose-Einstein equilibria (Eq. feq_dist, epsilon = +-1)    */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * f_eq = A / (z^-1 exp(U.p / T) + epsilon), z = exp(mu / T), with the fixed
+ * normalisation A = 1/(2 pi) (the paper writes f_eq only up to a factor;
+ * with it epsilon -> 0 gives the Maxwell-Juttner form used above, with
+ * z = n / T^2).  Since f_eq depends on p only through U.p / T, its rank-k
+ * moment is A T^(k+1) k! G_k(z) times the same angular tensor as the
+ * Maxwell-Juttner one, with the radial integral
+ *   G_k(z) = (1/k!) int_0^inf x^k / (z^-1 e^x + epsilon) dx
+ *          = z (MJ), -Li_{k+1}(-z) (FD), Li_{k+1}(z) (BE, z <= 1).
+ * Hence n = T^2 G_1(z), and the rank-k moment equals the Maxwell-Juttner one
+ * at the same (n, T, U) times phi_k = G_k(z) / G_1(z); eps = 2 n T phi_2,
+ * P = eps / 2 as before.  Statistics: 0 MJ, 1 FD, 2 BE.
+ */
+enum { STAT_MJ = 0, STAT_FD = 1, STAT_BE = 2 };
+
+/* zeta(n) for integer n != 1: n >= 2 by a direct sum with the
+ * Euler-Maclaurin tail; zeta(0) = -1/2; zeta(-m) = 0 for even m > 0 and
+ * zeta(1 - 2k) = (-1)^k 2 (2k-1)! zeta(2k) / (2 pi)^(2k). */
+static ld zeta_eval(int n)
+{
+    if (n >= 2) {
+        const int M = 1000;
+        ld s = 0.0L;
+        for (int j = M - 1; j >= 1; --j) s += powl((ld)j, (ld)-n);
+        ld Mn = powl((ld)M, (ld)-n);
+        s += powl((ld)M, (ld)(1 - n)) / (n - 1) + 0.5L * Mn + n * Mn / (12.0L * M)
+           - (ld)n * (n + 1) * (n + 2) * Mn / (720.0L * M * M * M);
+        return s;
+    }
+    if (n == 0) return -0.5L;
+    int m = -n;
+    if (m % 2 == 0) return 0.0L;
+    int k = (m + 1) / 2;
+    ld f = 1.0L;
+    for (int i = 2; i <= 2 * k - 1; ++i) f *= i;
+    return ((k & 1) ? -1.0L : 1.0L) * 2.0L * f * zeta_eval(2 * k) / powl(2.0L * PI_L, (ld)(2 * k));
+}
+
+/* zeta(n) for -ZMIN <= n <= ZMAX, tabulated once when the library loads. */
+#define ZMIN 80
+#define ZMAX 24
+static ld zeta_tab[ZMIN + ZMAX + 1];
+__attribute__((constructor)) static void zeta_init(void)
+{
+    for (int n = -ZMIN; n <= ZMAX; ++n) zeta_tab[n + ZMIN] = n == 1 ? 0.0L : zeta_eval(n);
+}
+static ld zeta_int(int n) { return zeta_tab[n + ZMIN]; }
+
+static ld ipow(ld x, int e)
+{
+    ld r = 1.0L;
+    for (int i = 0; i < e; ++i) r *= x;
+    return r;
+}
+
+/* sum_{j>=1} (-1)^(j+1) x^j / j^s = -Li_s(-x) for 0 <= x <= 1, by the
+ * alternating-series acceleration of Cohen, Rodriguez Villegas and Zagier
+ * (their algorithm 1; the terms form a moment sequence). */
+static ld alt_polylog(int s, ld x)
+{
+    const int N = 40;
+    ld d = powl(3.0L + sqrtl(8.0L), (ld)N);
+    d = 0.5L * (d + 1.0L / d);
+    ld b = -1.0L, c = -d, sum = 0.0L, xp = 1.0L;
+    for (int k = 0; k < N; ++k) {
+        c = b - c;
+        xp *= x;
+        sum += c * xp / ipow((ld)(k + 1), s);
+        b = (ld)(k + N) * (ld)(k - N) * b / ((k + 0.5L) * (k + 1.0L));
+    }
+    return sum / d;
+}
+
+/* -Li_s(-x), x >= 0, s >= 1: the accelerated series for x <= 1, else the
+ * inversion formula
+ *   -Li_s(-x) = mu^s/s! + 2 sum_{j=1}^{s/2} eta(2j) mu^(s-2j)/(s-2j)! + (-1)^s Li_s(-1/x),
+ * mu = ln x, eta(2j) = (1 - 2^(1-2j)) zeta(2j). */
+static ld fd_polylog(int s, ld x)
+{
+    if (x <= 1.0L) return alt_polylog(s, x);
+    ld mu = logl(x), r = 0.0L, f = 1.0L;
+    for (int i = 2; i <= s; ++i) f *= i;
+    r = powl(mu, (ld)s) / f;
+    for (int j = 1; 2 * j <= s; ++j) {
+        ld g = 1.0L;
+        for (int i = 2; i <= s - 2 * j; ++i) g *= i;
+        r += 2.0L * (1.0L - powl(2.0L, (ld)(1 - 2 * j))) * zeta_int(2 * j) * powl(mu, (ld)(s - 2 * j)) / g;
+    }
+    return r - ((s & 1) ? -1.0L : 1.0L) * alt_polylog(s, 1.0L / x);
+}
+
+/* Li_s(x), 0 <= x <= 1, s >= 1: -ln(1 - x) for s = 1; the power series for
+ * x <= 1/2; else the expansion in mu = ln x (|mu| < 2 pi)
+ *   Li_s(e^mu) = sum_{j != s-1} zeta(s-j) mu^j/j! + mu^(s-1)/(s-1)! (H_{s-1} - ln(-mu)). */
+static ld be_polylog(int s, ld x)
+{
+    if (s == 1) return -log1pl(-x);
+    if (x <= 0.5L) {
+        ld sum = 0.0L, xp = 1.0L;
+        for (int j = 1; j < 200; ++j) {
+            xp *= x;
+            ld t = xp / ipow((ld)j, s);
+            sum += t;
+            if (t < 1e-24L * sum) break;
+        }
+        return sum;
+    }
+    if (x >= 1.0L) return zeta_int(s);
+    ld mu = logl(x), sum = 0.0L, term = 1.0L;   /* term = mu^j / j! */
+    for (int j = 0; j < 60 && s - j >= -ZMIN; ++j) {
+        if (j == s - 1) {
+            ld H = 0.0L;
+            for (int i = 1; i <= s - 1; ++i) H += 1.0L / i;
+            sum += term * (H - logl(-mu));
+        } else {
+            sum += zeta_int(s - j) * term;
+        }
+        term *= mu / (j + 1);
+    }
+    return sum;
+}
+
+/* G_k(z) of the statistics stat. */
+static ld qs_G(int k, ld z, int stat)
+{
+    if (stat == STAT_FD) return fd_polylog(k + 1, z);
+    if (stat == STAT_BE) return be_polylog(k + 1, z);
+    return z;
+}
+
+double orc_qs_G(int k, double z, int stat) { return (double)qs_G(k, z, stat); }
+
+/* z of the initial state (n, T): G_1(z) = n / T^2, by bisection in ln z
+ * (G_1 increases with z).  Returns 0, or 1 without a solution (BE above
+ * G_1(1) = zeta(2)). */
+static int qs_z_of_nT(ld n, ld T, int stat, ld* z)
+{
+    ld target = n / (T * T);
+    if (stat == STAT_MJ) { *z = target; return 0; }
+    ld lo = -80.0L, hi = stat == STAT_BE ? 0.0L : 80.0L;
+    if (!(qs_G(1, expl(hi), stat) >= target)) return 1;
+    for (int it = 0; it < 120; ++it) {
+        ld mid = 0.5L * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (qs_G(1, expl(mid), stat) < target) lo = mid; else hi = mid;
+    }
+    *z = expl(0.5L * (lo + hi));
+    return 0;
+}
+
+/* eps^2 / n^3 of the equilibrium of fugacity e^y: 4 G_2^2 / G_1^3. */
+static ld qs_h(ld y, int stat)
+{
+    ld z = expl(y), g1 = qs_G(1, z, stat), g2 = qs_G(2, z, stat);
+    return 4.0L * g2 * g2 / (g1 * g1 * g1);
+}
+
+/* Temperature, fugacity and moment factors of a Landau frame (n, eps):
+ * z solves 4 G_2(z)^2 / G_1(z)^3 = eps^2 / n^3 (decreasing in z; bisection
+ * in ln z), T = sqrt(n / G_1(z)), phi_k = G_k / G_1 for k <= kmax.
+ * Returns 0, or 1 without a solution (FD below the degenerate limit 8/9, BE
+ * below the value at z = 1). */
+static int qs_frame(ld n, ld eps, int stat, int kmax, ld* T, ld* z, ld* phi)
+{
+    if (stat == STAT_MJ) {
+        *T = eps / (2.0L * n);
+        *z = n / (*T * *T);
+        for (int k = 0; k <= kmax; ++k) phi[k] = 1.0L;
+        return 0;
+    }
+    ld r = eps * eps / (n * n * n);
+    ld lo = -80.0L, hi = stat == STAT_BE ? 0.0L : 80.0L;
+    if (!(qs_h(hi, stat) <= r)) return 1;
+    for (int it = 0; it < 120; ++it) {
+        ld mid = 0.5L * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (qs_h(mid, stat) > r) lo = mid; else hi = mid;
+    }
+    *z = expl(0.5L * (lo + hi));
+    ld G1 = qs_G(1, *z, stat);
+    *T = sqrtl(n / G1);
+    for (int k = 0; k <= kmax; ++k) phi[k] = qs_G(k, *z, stat) / G1;
+    return 0;
+}
+
+/* The discrete truncated equilibrium of (n, T, U) under statistics stat
+ * (rlbm_oracle's Maxwell-Juttner route with the factors phi_k); returns 1
+ * if (n, T) has no equilibrium of that statistics. */
+int orc_feq_qs(const orc_quad* q, double n, double T, double ux, double uy, int stat, double* feq)
+{
+    ld U[3] = {sqrtl(1.0L + (ld)ux * ux + (ld)uy * uy), ux, uy};
+    ld z, phi[17];
+    if (qs_z_of_nT(n, T, stat, &z)) return 1;
+    ld G1 = qs_G(1, z, stat);
+    for (int k = 0; k <= q->N + 1 && k < 17; ++k) phi[k] = stat == STAT_MJ ? 1.0L : qs_G(k, z, stat) / G1;
+    feq_site(q, n, T, U, phi, feq);
+    return 0;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -426,6 +631,19 @@ static int landau_site(const double* mom, ld* out)
     return 0;
 }
 
+/* Landau frame and statistics of nine moments: out8 = (n, eps, U^x, U^y, T,
+ * U^0, z, phi_2); returns 1 for a state without such an equilibrium. */
+int orc_qs_landau(const double* mom, int stat, double* out8)
+{
+    ld o[6], T = 0, z = 0, phi[3] = {0, 0, 0};
+    int bad = landau_site(mom, o) || qs_frame(o[0], o[1], stat, 2, &T, &z, phi);
+    out8[0] = (double)o[0]; out8[1] = (double)o[1]; out8[2] = (double)o[2]; out8[3] = (double)o[3];
+    out8[4] = (double)T; out8[5] = (double)o[5]; out8[6] = (double)z; out8[7] = (double)phi[2];
+    if (bad)
+        for (int i = 0; i < 8; ++i) out8[i] = NAN;
+    return bad;
+}
+
 int orc_landau(const double* mom, double* out6)
 {
     ld o[6];
@@ -461,6 +679,7 @@ typedef struct {
     double tau, dt;
     double *f, *fs;             /* [nvel][ny][nx] */
     double *f0;                 /* initial populations (FIXED edges), or NULL */
+    int stat;                   /* STAT_MJ, STAT_FD, STAT_BE */
     long nonphys;
 } orc_sim;
 
@@ -478,32 +697,38 @@ static int reversed(const orc_quad* q, int v)
     return i * q->K + (j + q->K / 2) % q->K;
 }
 
-static void site_eq(const orc_quad* q, double n, double T, double ux, double uy, double* out, long stride)
+static int site_eq(const orc_quad* q, double n, double T, double ux, double uy, int stat, double* out, long stride)
 {
     double tmp[4096];
     double* buf = q->nvel <= 4096 ? tmp : (double*)malloc(sizeof(double) * q->nvel);
-    ld U[3] = {sqrtl(1.0L + (ld)ux * ux + (ld)uy * uy), ux, uy};
-    feq_site(q, n, T, U, buf);
+    int bad = orc_feq_qs(q, n, T, ux, uy, stat, buf);
     for (int v = 0; v < q->nvel; ++v) out[(long)v * stride] = buf[v];
     if (buf != tmp) free(buf);
+    return bad;
 }
 
 /* Initial populations: the truncated equilibrium of the given fields
  * (host arrays [ny][nx]; u = spatial part U^i of the four-velocity). */
 orc_sim* orc_sim_new(const orc_quad* q, int nx, int ny, const double* n, const double* T,
-                     const double* ux, const double* uy, double tau, double dt, int bcx, int bcy)
+                     const double* ux, const double* uy, double tau, double dt, int bcx, int bcy, int stat)
 {
     if (!q || nx < 1 || ny < 1) return NULL;
+    if (stat < STAT_MJ || stat > STAT_BE) return NULL;
     if (bcx < BC_PERIODIC || bcx > BC_FIXED || bcy < BC_PERIODIC || bcy > BC_FIXED) return NULL;
     if ((bcx == BC_WALL || bcy == BC_WALL) && (q->K % 2)) return NULL;   /* no reversed velocity */
     orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
-    s->q = q; s->nx = nx; s->ny = ny; s->bcx = bcx; s->bcy = bcy; s->tau = tau; s->dt = dt;
+    s->q = q; s->nx = nx; s->ny = ny; s->bcx = bcx; s->bcy = bcy; s->tau = tau; s->dt = dt; s->stat = stat;
     long S = (long)nx * ny;
     s->f = (double*)malloc(sizeof(double) * S * q->nvel);
     s->fs = (double*)malloc(sizeof(double) * S * q->nvel);
-    #pragma omp parallel for schedule(static)
+    long bad = 0;
+    #pragma omp parallel for schedule(static) reduction(+ : bad)
     for (long i = 0; i < S; ++i)
-        site_eq(q, n[i], T[i], ux ? ux[i] : 0.0, uy ? uy[i] : 0.0, s->f + i, S);
+        bad += site_eq(q, n[i], T[i], ux ? ux[i] : 0.0, uy ? uy[i] : 0.0, stat, s->f + i, S);
+    if (bad) {   /* (n, T) without an equilibrium of this statistics */
+        free(s->f); free(s->fs); free(s);
+        return NULL;
+    }
     if (bcx == BC_FIXED || bcy == BC_FIXED) {
         s->f0 = (double*)malloc(sizeof(double) * S * q->nvel);
         memcpy(s->f0, s->f, sizeof(double) * S * q->nvel);
@@ -586,7 +811,13 @@ static void collide_pass(orc_sim* s)
                 continue;
             }
             ld U[3] = {o[5], o[2], o[3]};
-            feq_site(q, o[0], o[4], U, feq);
+            ld Tq, zq, phi[17];
+            if (qs_frame(o[0], o[1], s->stat, q->N < 16 ? q->N : 16, &Tq, &zq, phi)) {
+                ++bad;   /* no equilibrium of this statistics: streamed without collision */
+                for (int v = 0; v < q->nvel; ++v) s->f[(long)v * S + i] = s->fs[(long)v * S + i];
+                continue;
+            }
+            feq_site(q, o[0], Tq, U, phi, feq);
             for (int v = 0; v < q->nvel; ++v) {
                 double om = rate * (double)(o[5] - o[2] * (ld)q->cth[v] - o[3] * (ld)q->sth[v]);
                 double fsv = s->fs[(long)v * S + i];
