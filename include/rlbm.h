@@ -60,6 +60,7 @@ enum { RLBM_F64 = 0, RLBM_F32 = 1 };                     /* population storage *
  * WALL and FIXED run on the tile kernel (RLBM_KERNEL_TILE). */
 enum { RLBM_BC_PERIODIC = 0, RLBM_BC_CLAMP = 1, RLBM_BC_WALL = 2, RLBM_BC_FIXED = 3 };   /* per axis */
 enum { RLBM_KERNEL_AUTO = 0, RLBM_KERNEL_TILE = 1, RLBM_KERNEL_PUSH = 2 };   /* step kernel */
+enum { RLBM_STAT_MJ = 0, RLBM_STAT_FERMI = 1, RLBM_STAT_BOSE = 2 };           /* equilibrium statistics */
 
 /*
  * Build the quadrature of Sec. 2.3 (Eq. off-lattice-quad) on the host and
@@ -403,6 +404,25 @@ int rlbm_device_landau(int count, const double* mom, double* out);
 
 /* Message for the last failing call on ctx (static storage of the context). */
 const char* rlbm_last_error(rlbm_ctx ctx);
+
+/*
+ * Equilibrium statistics of the context (Sec. 2.1, Eq. feq_dist:
+ * f_eq proportional to 1 / (z^-1 exp(U.p / T) + epsilon), z = exp(mu / T)):
+ *   RLBM_STAT_MJ     Maxwell-Juttner (epsilon = 0; the default);
+ *   RLBM_STAT_FERMI  Fermi-Dirac (epsilon = 1);
+ *   RLBM_STAT_BOSE   Bose-Einstein (epsilon = -1).
+ * The normalisation is 1/(2 pi) for all three, so that n = T^2 G_1(z) with
+ * G_k(z) = z, -Li_{k+1}(-z), Li_{k+1}(z); the truncated expansion uses the
+ * same basis and quadrature, its rank-k coefficients scaled by
+ * G_k(z) / G_1(z).  Each step takes (n, eps, U) from the Landau frame, then
+ * z from eps^2 / n^3 = 4 G_2^2 / G_1^3 and T = sqrt(n / G_1); a frame without
+ * such an equilibrium (Fermi-Dirac below the degenerate limit eps^2 / n^3 =
+ * 8/9, Bose-Einstein above condensation) is non-physical.  Takes effect at
+ * the next rlbm_init_fields (which, for Bose-Einstein, rejects sites with
+ * n / T^2 >= zeta(2)) and applies to rlbm_host_feq at once.  Fermi-Dirac and
+ * Bose-Einstein run on the tile kernel.  RLBM_EINVAL for another value.
+ */
+int rlbm_set_statistics(rlbm_ctx ctx, int statistics);
 
 /* Release the context, its tables and any library-owned workspace. */
 int rlbm_destroy(rlbm_ctx ctx);

@@ -60,6 +60,8 @@ void free_tables(rlbm_ctx c)
     if (c->d_G) (void)hipFree(c->d_G);
     if (c->d_Pc) (void)hipFree(c->d_Pc);
     if (c->d_corr) (void)hipFree(c->d_corr);
+    if (c->d_zeta) (void)hipFree(c->d_zeta);
+    c->d_zeta = nullptr;
     c->d_srec = nullptr; c->d_crec = nullptr; c->d_sgn = nullptr; c->d_veld = nullptr; c->d_corr = nullptr; c->d_G = nullptr; c->d_Pc = nullptr;
 }
 
@@ -133,7 +135,7 @@ bool finite_arr(const double* a, long long S)
 int resolve_kernel(rlbm_ctx c)
 {
     if (c->kern != RLBM_KERNEL_AUTO) return c->kern;
-    if (special_bc(c->bcx, c->bcy)) return RLBM_KERNEL_TILE;
+    if (general_step(c->bcx, c->bcy, c->fstat)) return RLBM_KERNEL_TILE;
     return c->q.nvel >= RLBM_PUSH_MIN_NVEL ? RLBM_KERNEL_PUSH : RLBM_KERNEL_TILE;
 }
 
@@ -149,6 +151,8 @@ SCParams make_params(rlbm_ctx c, int waves)
     p.Pc = c->d_Pc;
     p.nx = c->nx; p.ny = c->ny; p.nvel = c->q.nvel; p.K = c->q.K; p.Np = c->q.Np; p.N = c->q.N;
     p.bcx = c->bcx; p.bcy = c->bcy; p.S = c->S; p.rate = c->rate; p.flag = c->d_flag;
+    p.stat = c->fstat;
+    p.ztab = c->d_zeta;
     const int chunk = (c->q.nvel + waves - 1) / waves;
     p.chunk = (chunk + RLBM_LB - 1) / RLBM_LB * RLBM_LB;
     p.band = RLBM_BAND_DEFAULT;
@@ -169,6 +173,7 @@ int rlbm_init_quadrature(rlbm_ctx* out, int n_radial, int n_angle, int order, in
         delete c;
         return rc;
     }
+    build_zeta_table(c->zeta);
     *out = c;
     return RLBM_OK;
 }
@@ -214,6 +219,10 @@ int rlbm_init_fields(rlbm_ctx c, int nx, int ny, const double* n, const double* 
         return fail(c, RLBM_EINVAL, "fields must be finite");
     for (long long i = 0; i < S; ++i)
         if (!(n[i] > 0.0) || !(T[i] > 0.0)) return fail(c, RLBM_EINVAL, "n and T must be positive");
+    if (c->stat == RLBM_STAT_BOSE)   // n = T^2 Li_2(z) <= T^2 zeta(2) for a Bose-Einstein equilibrium
+        for (long long i = 0; i < S; ++i)
+            if (!(n[i] / (T[i] * T[i]) < c->zeta[2 + RLBM_ZMIN]))
+                return fail(c, RLBM_EINVAL, "no Bose-Einstein equilibrium: n / T^2 must stay below zeta(2)");
 
     // From here on the context holds no usable state until this call
     // succeeds: a failure below leaves rlbm_step and rlbm_moments returning
@@ -249,6 +258,7 @@ int rlbm_init_fields(rlbm_ctx c, int nx, int ny, const double* n, const double* 
         c->ws_bytes = L.total;
     }
     c->nx = nx; c->ny = ny; c->S = S; c->prec = precision;
+    c->fstat = c->stat;
     c->bcx = bc_x; c->bcy = bc_y; c->tau = tau; c->dt = dt;
     c->rate = std::isinf(tau) ? 0.0 : dt / tau;
     c->st = st;
@@ -276,6 +286,9 @@ int rlbm_init_fields(rlbm_ctx c, int nx, int ny, const double* n, const double* 
     if ((e = hipMemcpy(c->d_G, c->q.G.data(), c->q.G.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(c, e, "table upload");
     if ((e = hipMemcpy(c->d_Pc, c->q.Pc.data(), c->q.Pc.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(c, e, "table upload");
+    if ((e = hipMalloc(&c->d_zeta, sizeof(c->zeta))) != hipSuccess) return fail(c, RLBM_ENOMEM, "table alloc");
+    if ((e = hipMemcpy(c->d_zeta, c->zeta, sizeof(c->zeta), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(c, e, "table upload");
     // kernel tables, padded with null entries (zero weights, spare plane),
     // for both step kernels
@@ -305,7 +318,7 @@ int rlbm_init_fields(rlbm_ctx c, int nx, int ny, const double* n, const double* 
             return hip_fail(c, e, "spare clear");
     }
     e = launch_init(precision, nmax_of(c->q.N), c->d_fields, c->f[0], c->d_veld, c->d_G, c->d_Pc, nx, ny,
-                    c->q.nvel, c->q.K, c->q.Np, st);
+                    c->q.nvel, c->q.K, c->q.Np, c->fstat, c->d_zeta, st);
     if (e != hipSuccess) return hip_fail(c, e, "init kernel");
     e = launch_edges(precision, c->f[0], c->d_edges, nx, ny, c->q.nvel, st);
     if (e != hipSuccess) return hip_fail(c, e, "edge copy kernel");
@@ -339,7 +352,8 @@ int rlbm_step(rlbm_ctx c, int nsteps)
     if (!c->have_fields) return fail(c, RLBM_ESTATE, "rlbm_step before rlbm_init_fields");
     if (nsteps < 0) return fail(c, RLBM_EINVAL, "nsteps < 0");
     if (resolve_kernel(c) == RLBM_KERNEL_PUSH) {
-        if (special_bc(c->bcx, c->bcy)) return fail(c, RLBM_EINVAL, "walls and fixed edges need the tile kernel");
+        if (general_step(c->bcx, c->bcy, c->fstat))
+            return fail(c, RLBM_EINVAL, "walls, fixed edges and quantum statistics need the tile kernel");
         if (!c->d_prec) return fail(c, RLBM_ESTATE, "push kernel tables missing");
         hipError_t e;
         if (!c->pvalid && nsteps > 0) {
@@ -484,8 +498,8 @@ int rlbm_set_kernel(rlbm_ctx c, int kind)
     if (!c) return RLBM_EINVAL;
     if (kind != RLBM_KERNEL_AUTO && kind != RLBM_KERNEL_TILE && kind != RLBM_KERNEL_PUSH)
         return fail(c, RLBM_EINVAL, "unknown kernel kind");
-    if (kind == RLBM_KERNEL_PUSH && c->have_fields && special_bc(c->bcx, c->bcy))
-        return fail(c, RLBM_EINVAL, "walls and fixed edges need the tile kernel");
+    if (kind == RLBM_KERNEL_PUSH && c->have_fields && general_step(c->bcx, c->bcy, c->fstat))
+        return fail(c, RLBM_EINVAL, "walls, fixed edges and quantum statistics need the tile kernel");
     c->kern = kind;
     c->pvalid = 0;
     return RLBM_OK;
@@ -526,6 +540,8 @@ int rlbm_host_feq(rlbm_ctx c, double n, double T, double ux, double uy, double* 
     build_vel_table(c->q, 1.0, vd);
     const double U0 = std::sqrt(1.0 + ux * ux + uy * uy);
     const int GS = (RLBM_NMAX + 1) * (RLBM_NMAX + 1);
+    double phi[RLBM_NMAX + 1];
+    if (qs_phi_of_nT(n, T, c->stat, RLBM_NMAX, (const double*)c->zeta, phi)) return RLBM_ENONPHYS;
     for (int i = 0; i < c->q.Np; ++i) {
         double cf[RLBM_NT];
         shell_coeffs<RLBM_NMAX>(c->q.G.data() + (size_t)i * GS, c->q.Pc.data(), n, T, U0, ux, uy,
@@ -536,7 +552,8 @@ int rlbm_host_feq(rlbm_ctx c, double n, double T, double ux, double uy, double* 
                                         cf[2 * m - 1] = cm;
                                         cf[2 * m] = sm;
                                     }
-                                });
+                                },
+                                c->stat != RLBM_STAT_MJ ? phi : nullptr);
         for (int j = 0; j < c->q.K; ++j) {
             const int v = i * c->q.K + j;
             double fe = 0.0;
@@ -544,6 +561,15 @@ int rlbm_host_feq(rlbm_ctx c, double n, double T, double ux, double uy, double* 
             feq[v] = fe;
         }
     }
+    return RLBM_OK;
+}
+
+int rlbm_set_statistics(rlbm_ctx c, int statistics)
+{
+    if (!c) return RLBM_EINVAL;
+    if (statistics != RLBM_STAT_MJ && statistics != RLBM_STAT_FERMI && statistics != RLBM_STAT_BOSE)
+        return fail(c, RLBM_EINVAL, "unknown statistics");
+    c->stat = statistics;
     return RLBM_OK;
 }
 

@@ -71,7 +71,7 @@ __device__ __forceinline__ int wrap_idx(int i, int n, int bc)
 // block a few tiles wide and P.band tall, so that the upwind row a tile reads
 // is read by its neighbour in the block at about the same time (L2 reuse even
 // when one grid row of all velocities exceeds the L2).
-template <typename TS, typename TC, int NM, int VPT, bool BC = false>
+template <typename TS, typename TC, int NM, int VPT, bool GEN = false>
 __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restrict__ fout,
                                         const SRec<TC>* srec_, const CRec<TC, NM>* crec_, const double* Gtab_,
                                         const double* Pc_, const SCParams& P, int tile, unsigned char* smem)
@@ -112,7 +112,7 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
     // select a wrapped or clamped column per lane.
     // WALL and FIXED axes: upwind points outside the grid take the boundary's
     // values (the rows next to such an edge are edge tiles too)
-    const bool bxs = BC && P.bcx >= RLBM_BC_WALL, bys = BC && P.bcy >= RLBM_BC_WALL;
+    const bool bxs = GEN && P.bcx >= RLBM_BC_WALL, bys = GEN && P.bcy >= RLBM_BC_WALL;
     const bool interior = tx > 0 && (tx + 1) * 64 < P.nx && !(bys && (ty == 0 || ty == P.ny - 1));
     constexpr unsigned ES = sizeof(TS);
     const unsigned ocb = (unsigned)xc * ES;
@@ -161,7 +161,7 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
         } else {
             const unsigned osb = cneg ? opb : omb;
             r[0] = ld(p0, ocb); r[1] = ld(p0, osb); r[2] = ld(p1, ocb); r[3] = ld(p1, osb);
-            if (BC && (bxs || bys)) {
+            if (GEN && (bxs || bys)) {
                 const bool xo = bxs && (cneg ? xc + 1 >= P.nx : xc == 0);   // this lane's upwind column is outside
                 const bool yo = bys && (sneg ? ty + 1 >= P.ny : ty == 0);   // the upwind row is outside
                 if (xo || yo) {
@@ -253,7 +253,16 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
         mom[j] = s;
     }
     if (NMOM == 8) mom[8] = mom[3] - mom[6];
-    const Frame fr = landau_frame(mom);
+    Frame fr = landau_frame(mom);
+    // Fermi-Dirac / Bose-Einstein: temperature and moment factors of the
+    // frame (no equilibrium of that statistics counts as non-physical)
+    double phi[NM + 1];
+    if (GEN && P.stat != RLBM_STAT_MJ && fr.ok) {
+        double Tq = 0.0;
+        if (qs_frame(fr.n, fr.eps, P.stat, NM, P.ztab, &Tq, phi)) fr.ok = 0;
+        fr.T = Tq;
+    }
+    const double* phip = (GEN && P.stat != RLBM_STAT_MJ) ? phi : nullptr;
     if (!fr.ok && active) atomicOr(P.flag, 1);
     // a site without a physical frame is streamed without collision (its
     // frame may hold NaN, so the rates are zeroed rather than scaled)
@@ -273,7 +282,8 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
                                  ci[(2 * mm - 1) * 64] = (TC)cm;
                                  ci[(2 * mm) * 64] = (TC)sm;
                              }
-                         });
+                         },
+                         phip);
     }
     __syncthreads();
 
@@ -332,9 +342,10 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
         phase4(std::false_type{});
 }
 
-// BC: the instance with the boundary loads of WALL and FIXED axes (a
-// separate instance, so that the others keep their register budget).
-template <typename TS, typename TC, int NM, int VPT, bool BC>
+// GEN: the general instance, with the boundary loads of WALL and FIXED axes
+// and the Fermi-Dirac / Bose-Einstein equilibria (a separate instance, so
+// that the others keep their register budget).
+template <typename TS, typename TC, int NM, int VPT, bool GEN>
 __global__ __launch_bounds__(1024) void k_stream_collide(const TS* __restrict__ fin, TS* __restrict__ fout,
                                                          const SRec<TC>* __restrict__ srec,
                                                          const CRec<TC, NM>* __restrict__ crec,
@@ -342,7 +353,7 @@ __global__ __launch_bounds__(1024) void k_stream_collide(const TS* __restrict__ 
                                                          const double* __restrict__ Pc, SCParams P)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    sc_tile<TS, TC, NM, VPT, BC>(fin, fout, srec, crec, Gtab, Pc, P, xcd_remap(blockIdx.x, gridDim.x), smem);
+    sc_tile<TS, TC, NM, VPT, GEN>(fin, fout, srec, crec, Gtab, Pc, P, xcd_remap(blockIdx.x, gridDim.x), smem);
 }
 
 // Batched form: many independent problems advance one step in one
@@ -418,7 +429,8 @@ __global__ void k_reset_counters(int* counters)
 template <typename TS, int NM>
 __global__ __launch_bounds__(256) void k_init(const double* __restrict__ fields, TS* __restrict__ f,
                                               const VelRec<double>* __restrict__ vel, const double* __restrict__ G,
-                                              const double* __restrict__ Pc, long long S, int K, int Np)
+                                              const double* __restrict__ Pc, long long S, int K, int Np, int stat,
+                                              const double* __restrict__ ztab)
 {
     constexpr int NT = 2 * NM + 1;
     constexpr int GS = (RLBM_NMAX + 1) * (RLBM_NMAX + 1);
@@ -426,6 +438,11 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ fields,
     if (s >= S) return;
     const double n = fields[s], T = fields[S + s], ux = fields[2 * S + s], uy = fields[3 * S + s];
     const double U0 = sqrt(1.0 + ux * ux + uy * uy);
+    // quantum statistics: moment factors of (n, T) (the host has checked
+    // that an equilibrium exists)
+    double phi[NM + 1];
+    if (stat != RLBM_STAT_MJ) (void)qs_phi_of_nT(n, T, stat, NM, ztab, phi);
+    const double* phip = stat != RLBM_STAT_MJ ? phi : nullptr;
     for (int i = 0; i < Np; ++i) {
         double c[NT];
         shell_coeffs<NM>(G + (size_t)i * GS, Pc, n, T, U0, ux, uy, [&](int m, double cm, double sm) {
@@ -435,7 +452,7 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ fields,
                 c[2 * m - 1] = cm;
                 c[2 * m] = sm;
             }
-        });
+        }, phip);
         for (int j = 0; j < K; ++j) {
             const int v = i * K + j;
             double fe = 0.0;
@@ -483,7 +500,7 @@ __global__ __launch_bounds__(256) void k_fields(const TS* __restrict__ f, const 
     if (threadIdx.x < 4) partials[(size_t)blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-template <typename TS, typename TC, int NM, int VPT, bool BC>
+template <typename TS, typename TC, int NM, int VPT, bool GEN>
 hipError_t launch_sc_b(int waves, const SCParams& p, hipStream_t st)
 {
     constexpr int NT = 2 * NM + 1;
@@ -492,14 +509,14 @@ hipError_t launch_sc_b(int waves, const SCParams& p, hipStream_t st)
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     static size_t configured = 0;
     if (lds > 64 * 1024 && lds > configured) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stream_collide<TS, TC, NM, VPT, BC>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stream_collide<TS, TC, NM, VPT, GEN>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         configured = lds;
     }
     const long long tiles = (long long)((p.nx + 63) / 64) * p.ny;
     if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_stream_collide<TS, TC, NM, VPT, BC>), dim3((unsigned)tiles), dim3(64 * waves), lds, st,
+    hipLaunchKernelGGL((k_stream_collide<TS, TC, NM, VPT, GEN>), dim3((unsigned)tiles), dim3(64 * waves), lds, st,
                        static_cast<const TS*>(p.fin), static_cast<TS*>(p.fout),
                        static_cast<const SRec<TC>*>(p.srec), static_cast<const CRec<TC, NM>*>(p.crec), p.G, p.Pc, p);
     return hipGetLastError();
@@ -508,7 +525,7 @@ hipError_t launch_sc_b(int waves, const SCParams& p, hipStream_t st)
 template <typename TS, typename TC, int NM, int VPT>
 hipError_t launch_sc_t(int waves, const SCParams& p, hipStream_t st)
 {
-    if (special_bc(p.bcx, p.bcy)) return launch_sc_b<TS, TC, NM, VPT, true>(waves, p, st);
+    if (general_step(p.bcx, p.bcy, p.stat)) return launch_sc_b<TS, TC, NM, VPT, true>(waves, p, st);
     return launch_sc_b<TS, TC, NM, VPT, false>(waves, p, st);
 }
 
@@ -597,13 +614,13 @@ int batch_grid_t(int waves, int max_np)
 
 template <typename TS>
 hipError_t launch_init_t(int nmax, const double* fields, void* f, const VelRec<double>* vel, const double* G,
-                         const double* Pc, long long S, int K, int Np, hipStream_t st)
+                         const double* Pc, long long S, int K, int Np, int stat, const double* ztab, hipStream_t st)
 {
     const unsigned blocks = (unsigned)((S + 255) / 256);
     switch (nmax) {
-        case 3: hipLaunchKernelGGL((k_init<TS, 3>), dim3(blocks), dim3(256), 0, st, fields, (TS*)f, vel, G, Pc, S, K, Np); break;
-        case 5: hipLaunchKernelGGL((k_init<TS, 5>), dim3(blocks), dim3(256), 0, st, fields, (TS*)f, vel, G, Pc, S, K, Np); break;
-        case 7: hipLaunchKernelGGL((k_init<TS, 7>), dim3(blocks), dim3(256), 0, st, fields, (TS*)f, vel, G, Pc, S, K, Np); break;
+        case 3: hipLaunchKernelGGL((k_init<TS, 3>), dim3(blocks), dim3(256), 0, st, fields, (TS*)f, vel, G, Pc, S, K, Np, stat, ztab); break;
+        case 5: hipLaunchKernelGGL((k_init<TS, 5>), dim3(blocks), dim3(256), 0, st, fields, (TS*)f, vel, G, Pc, S, K, Np, stat, ztab); break;
+        case 7: hipLaunchKernelGGL((k_init<TS, 7>), dim3(blocks), dim3(256), 0, st, fields, (TS*)f, vel, G, Pc, S, K, Np, stat, ztab); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -727,12 +744,13 @@ hipError_t launch_edges(int prec, const void* f, void* edges, int nx, int ny, in
 }
 
 hipError_t launch_init(int prec, int nmax, const double* fields, void* f, const VelRec<double>* vel, const double* G,
-                       const double* Pc, int nx, int ny, int nvel, int K, int Np, hipStream_t st)
+                       const double* Pc, int nx, int ny, int nvel, int K, int Np, int stat, const double* ztab,
+                       hipStream_t st)
 {
     (void)nvel;
     const long long S = (long long)nx * ny;
-    if (prec == RLBM_F64) return launch_init_t<double>(nmax, fields, f, vel, G, Pc, S, K, Np, st);
-    if (prec == RLBM_F32) return launch_init_t<float>(nmax, fields, f, vel, G, Pc, S, K, Np, st);
+    if (prec == RLBM_F64) return launch_init_t<double>(nmax, fields, f, vel, G, Pc, S, K, Np, stat, ztab, st);
+    if (prec == RLBM_F32) return launch_init_t<float>(nmax, fields, f, vel, G, Pc, S, K, Np, stat, ztab, st);
     return hipErrorInvalidValue;
 }
 

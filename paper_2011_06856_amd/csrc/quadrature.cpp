@@ -178,3 +178,49 @@ void build_vel_table(const HostQuad& q, double dt, std::vector<VelRec<double>>& 
         }
     }
 }
+
+// Riemann zeta at integers for the radial integrals of the quantum
+// statistics: n >= 2 by the sum to 63 plus the Euler-Maclaurin tail (four
+// Bernoulli terms; error below 1e-21), zeta(0) = -1/2, and for m > 0
+// zeta(-m) = 0 (m even) or (-1)^k 2 (2k-1)! zeta(2k) / (2 pi)^(2k) with
+// m = 2k - 1 (the functional equation).
+namespace {
+double zeta_pos(int n)
+{
+    const int M = 64;
+    double s = 0.0;
+    for (int j = M - 1; j >= 1; --j) s += std::pow((double)j, -n);
+    const double B[4] = {1.0 / 6.0, -1.0 / 30.0, 1.0 / 42.0, -1.0 / 30.0};   // B_2, B_4, B_6, B_8
+    double tail = std::pow((double)M, 1 - n) / (n - 1) + 0.5 * std::pow((double)M, -n);
+    double fact = 1.0, rise = 1.0;
+    for (int k = 1; k <= 4; ++k) {
+        fact *= (2.0 * k - 1.0) * (2.0 * k);                                  // (2k)!
+        rise *= (k == 1) ? n : (double)(n + 2 * k - 3) * (n + 2 * k - 2);    // n (n+1) ... (n+2k-2)
+        tail += B[k - 1] / fact * rise * std::pow((double)M, -n - 2 * k + 1);
+    }
+    return s + tail;
+}
+}  // namespace
+
+void build_zeta_table(double* ztab)
+{
+    const double pi = 3.14159265358979323846;
+    for (int n = -RLBM_ZMIN; n <= RLBM_ZMAX; ++n) {
+        double z;
+        if (n >= 2) {
+            z = zeta_pos(n);
+        } else if (n == 1) {
+            z = 0.0;   // pole, never used
+        } else if (n == 0) {
+            z = -0.5;
+        } else if ((-n) % 2 == 0) {
+            z = 0.0;
+        } else {
+            const int k = (1 - n) / 2;
+            double f = 1.0;
+            for (int i = 2; i <= 2 * k - 1; ++i) f *= i;
+            z = ((k & 1) ? -2.0 : 2.0) * f * zeta_pos(2 * k) / std::pow(2.0 * pi, 2 * k);
+        }
+        ztab[n + RLBM_ZMIN] = z;
+    }
+}

@@ -156,7 +156,7 @@ __host__ __device__ inline Frame landau_frame(const double* m)
 // harmonics above the order come out as zero.
 template <int NM, typename PT, typename Emit>
 __host__ __device__ inline void shell_coeffs(PT Gs, PT Pc, double n, double T, double U0, double Ux, double Uy,
-                                             Emit emit)
+                                             Emit emit, const double* phi = nullptr)
 {
     const double u2 = U0 * U0;
     double zr = 1.0, zi = 0.0;   // (U^x + i U^y)^m
@@ -172,7 +172,9 @@ __host__ __device__ inline void shell_coeffs(PT Gs, PT Pc, double n, double T, d
 #pragma unroll
             for (int l = 1; 2 * l <= r; ++l) pk = pk * u2 + pc[l];
             if (r & 1) pk *= U0;
-            acc += Gs[m * (RLBM_NMAX + 1) + r] * nTk * pk;
+            // Fermi-Dirac / Bose-Einstein: the radial moment of power m + r
+            // scaled by phi[m + r] (qs_frame below)
+            acc += Gs[m * (RLBM_NMAX + 1) + r] * nTk * pk * (phi ? phi[m + r] : 1.0);
             nTk *= T;
         }
         emit(m, acc * zr, acc * zi);
@@ -181,6 +183,175 @@ __host__ __device__ inline void shell_coeffs(PT Gs, PT Pc, double n, double T, d
         zi = zr * Uy + zi * Ux;
         zr = nzr;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Fermi-Dirac and Bose-Einstein equilibria (Eq. feq_dist with epsilon = +1,
+// -1): f_eq = (1/2pi) / (z^-1 exp(U.p/T) + epsilon).  As f_eq depends on p
+// only through U.p/T, the moment of radial power k is the Maxwell-Juttner one
+// at the same (n, T, U) times phi_k = G_k(z) / G_1(z), with the radial
+// integrals G_k(z) = (1/k!) int_0^inf x^k / (z^-1 e^x + epsilon) dx, i.e.
+// -Li_{k+1}(-z) (FD) and Li_{k+1}(z) (BE, z <= 1); n = T^2 G_1(z), eps =
+// 2 n T phi_2.  ztab: zeta(n) for n = -RLBM_ZMIN .. RLBM_ZMAX (built by
+// build_zeta_table; zeta(1) unused).
+// ---------------------------------------------------------------------------
+#define RLBM_ZMIN 40
+#define RLBM_ZMAX 12
+#define RLBM_NZETA (RLBM_ZMIN + RLBM_ZMAX + 1)
+void build_zeta_table(double* ztab);   // quadrature.cpp
+
+__host__ __device__ inline double ipow_d(double x, int e)
+{
+    double r = 1.0;
+    for (int i = 0; i < e; ++i) r *= x;
+    return r;
+}
+
+// sum_{j>=1} (-1)^(j+1) x^j / j^s for 0 <= x <= 1 (= -Li_s(-x)): the
+// alternating-series acceleration of Cohen, Rodriguez Villegas and Zagier
+// (algorithm 1), 28 terms (error below 5.8^-28 of the sum).
+__host__ __device__ inline double qs_alt(int s, double x)
+{
+    constexpr int N = 28;
+    const double e = 5.828427124746190;   // 3 + sqrt(8)
+    double d = ipow_d(e, N);
+    d = 0.5 * (d + 1.0 / d);
+    double b = -1.0, c = -d, sum = 0.0, xp = 1.0;
+    for (int k = 0; k < N; ++k) {
+        c = b - c;
+        xp *= x;
+        sum += c * xp / ipow_d((double)(k + 1), s);
+        b = (double)(k + N) * (double)(k - N) * b / ((k + 0.5) * (k + 1.0));
+    }
+    return sum / d;
+}
+
+// G_k(z) for statistics stat (RLBM_STAT_*), k >= 0.
+template <typename ZT>
+__host__ __device__ inline double qs_G(int k, double z, int stat, ZT ztab)
+{
+    const int s = k + 1;
+    auto zeta = [&](int n) { return (double)ztab[n + RLBM_ZMIN]; };
+    if (stat == RLBM_STAT_FERMI) {
+        if (s == 1) return log1p(z);
+        if (z <= 1.0) return qs_alt(s, z);
+        // inversion: -Li_s(-z) = mu^s/s! + 2 sum_j eta(2j) mu^(s-2j)/(s-2j)! + (-1)^s Li_s(-1/z)
+        const double mu = log(z);
+        double f = 1.0, r;
+        for (int i = 2; i <= s; ++i) f *= i;
+        r = ipow_d(mu, s) / f;
+        for (int j = 1; 2 * j <= s; ++j) {
+            double g = 1.0;
+            for (int i = 2; i <= s - 2 * j; ++i) g *= i;
+            r += 2.0 * (1.0 - ipow_d(0.5, 2 * j - 1)) * zeta(2 * j) * ipow_d(mu, s - 2 * j) / g;
+        }
+        return r - ((s & 1) ? -1.0 : 1.0) * qs_alt(s, 1.0 / z);
+    }
+    if (stat == RLBM_STAT_BOSE) {
+        if (s == 1) return -log1p(-z);
+        if (z >= 1.0) return zeta(s);
+        if (z <= 0.5) {
+            double sum = 0.0, xp = 1.0;
+            for (int j = 1; j <= 64; ++j) {
+                xp *= z;
+                sum += xp / ipow_d((double)j, s);
+            }
+            return sum;
+        }
+        // expansion in mu = ln z: sum_{j != s-1} zeta(s-j) mu^j/j! + mu^(s-1)/(s-1)! (H_{s-1} - ln(-mu))
+        const double mu = log(z);
+        double sum = 0.0, term = 1.0;
+        for (int j = 0; j < 32 && s - j >= -RLBM_ZMIN; ++j) {
+            if (j == s - 1) {
+                double H = 0.0;
+                for (int i = 1; i <= s - 1; ++i) H += 1.0 / i;
+                sum += term * (H - log(-mu));
+            } else {
+                sum += zeta(s - j) * term;
+            }
+            term *= mu / (j + 1);
+        }
+        return sum;
+    }
+    return z;
+}
+
+// Safeguarded Newton in y = ln z for g(y) = target, g monotone with
+// derivative dg(y); [lo, hi] brackets the root.  Returns 0 or 1 without a
+// root in the bracket.
+template <typename G, typename DG>
+__host__ __device__ inline int qs_solve(G g, DG dg, double target, bool increasing, double lo, double hi, double y,
+                                        double* out)
+{
+    const double glo = g(lo) - target, ghi = g(hi) - target;
+    if (!(increasing ? (glo <= 0.0 && ghi >= 0.0) : (glo >= 0.0 && ghi <= 0.0))) return 1;
+    y = fmin(fmax(y, lo), hi);
+    for (int it = 0; it < 200; ++it) {
+        const double v = g(y) - target;
+        if (v == 0.0) break;
+        if ((v < 0.0) == increasing) lo = y; else hi = y;
+        const double d = dg(y);
+        double yn = y - v / d;
+        if (!(yn > lo && yn < hi)) yn = 0.5 * (lo + hi);   // Newton left the bracket: bisect
+        if (fabs(yn - y) <= 1e-15 * fmax(1.0, fabs(y)) || hi - lo <= 1e-15 * fmax(1.0, fabs(y))) {
+            y = yn;
+            break;
+        }
+        y = yn;
+    }
+    *out = y;
+    return 0;
+}
+
+// Temperature and moment factors phi[0..kmax] of a Landau frame (n, eps):
+// z from 4 G_2^2 / G_1^3 = eps^2 / n^3 (decreasing in z), T = sqrt(n / G_1).
+// Returns 0, or 1 without an equilibrium (FD below the degenerate limit,
+// BE above condensation).
+template <typename ZT>
+__host__ __device__ inline int qs_frame(double n, double eps, int stat, int kmax, ZT ztab, double* T, double* phi)
+{
+    if (stat == RLBM_STAT_MJ) {
+        *T = eps / (2.0 * n);
+        for (int k = 0; k <= kmax; ++k) phi[k] = 1.0;
+        return 0;
+    }
+    const double r = eps * eps / (n * n * n);
+    auto h = [&](double y) {
+        const double z = exp(y), g1 = qs_G(1, z, stat, ztab), g2 = qs_G(2, z, stat, ztab);
+        return 4.0 * g2 * g2 / (g1 * g1 * g1);
+    };
+    auto dh = [&](double y) {   // z d/dz G_k = G_{k-1}
+        const double z = exp(y), g0 = qs_G(0, z, stat, ztab), g1 = qs_G(1, z, stat, ztab),
+                     g2 = qs_G(2, z, stat, ztab);
+        return 4.0 * g2 * g2 / (g1 * g1 * g1) * (2.0 * g1 / g2 - 3.0 * g0 / g1);
+    };
+    double y;
+    const double hi = stat == RLBM_STAT_BOSE ? 0.0 : 60.0;
+    if (qs_solve(h, dh, r, false, -60.0, hi, fmin(log(4.0 / r), hi), &y)) return 1;
+    const double z = exp(y), g1 = qs_G(1, z, stat, ztab);
+    *T = sqrt(n / g1);
+    for (int k = 0; k <= kmax; ++k) phi[k] = qs_G(k, z, stat, ztab) / g1;
+    return !(finite_d(*T) && *T > 0.0);
+}
+
+// Moment factors phi[0..kmax] of the state (n, T): z from n = T^2 G_1(z).
+// Returns 0, or 1 without an equilibrium (BE above condensation).
+template <typename ZT>
+__host__ __device__ inline int qs_phi_of_nT(double n, double T, int stat, int kmax, ZT ztab, double* phi)
+{
+    if (stat == RLBM_STAT_MJ) {
+        for (int k = 0; k <= kmax; ++k) phi[k] = 1.0;
+        return 0;
+    }
+    auto g = [&](double y) { return qs_G(1, exp(y), stat, ztab); };
+    auto dg = [&](double y) { return qs_G(0, exp(y), stat, ztab); };
+    const double target = n / (T * T);
+    double y;
+    const double hi = stat == RLBM_STAT_BOSE ? 0.0 : 60.0;
+    if (qs_solve(g, dg, target, true, -60.0, hi, fmin(log(target), hi), &y)) return 1;
+    const double z = exp(y), g1 = qs_G(1, z, stat, ztab);
+    for (int k = 0; k <= kmax; ++k) phi[k] = qs_G(k, z, stat, ztab) / g1;
+    return 0;
 }
 
 // Kernel launch parameters.
@@ -197,6 +368,8 @@ struct SCParams {
     const double* Pc;
     int nx, ny, nvel, K, Np, N;
     int bcx, bcy;
+    int stat;              // RLBM_STAT_* of the equilibrium
+    const double* ztab;    // zeta table of the quantum statistics
     long long S;
     double rate;           // dt / tau (0 for tau = inf)
     int* flag;
@@ -225,6 +398,7 @@ static_assert(sizeof(BatchDesc) % 4 == 0, "BatchDesc is copied in 32-bit words")
 // A simulation context (the opaque rlbm_ctx of the C ABI).
 struct rlbm_ctx_s {
     HostQuad q;
+    double zeta[RLBM_NZETA];             // zeta table of the quantum statistics (host)
     std::string err;
     int have_fields = 0;
     int dev = -1;                        // device of the workspace (rlbm_init_fields)
@@ -248,6 +422,9 @@ struct rlbm_ctx_s {
     VelRec<double>* d_veld = nullptr;    // FP64 table for init and fields [nvel]
     double* d_G = nullptr;
     double* d_Pc = nullptr;
+    double* d_zeta = nullptr;            // zeta table (quantum statistics)
+    int stat = RLBM_STAT_MJ;             // statistics of the next rlbm_init_fields
+    int fstat = RLBM_STAT_MJ;            // statistics of the current fields
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     long long steps = 0;
     double* d_corr = nullptr;            // learned correction: w p^2 {cos, sin} 2th per velocity
@@ -270,11 +447,15 @@ SCParams make_params(rlbm_ctx c, int waves);   // capi.cpp
 // A WALL or FIXED axis: upwind points outside the grid need the tile
 // kernel's boundary loads.
 inline bool special_bc(int bcx, int bcy) { return bcx >= RLBM_BC_WALL || bcy >= RLBM_BC_WALL; }
+// A grid that needs the tile kernel's general instance (boundary loads,
+// quantum statistics).
+inline bool general_step(int bcx, int bcy, int stat) { return special_bc(bcx, bcy) || stat != RLBM_STAT_MJ; }
 
 // Launchers (kernels.hip).
 hipError_t launch_edges(int prec, const void* f, void* edges, int nx, int ny, int nvel, hipStream_t st);
 hipError_t launch_init(int prec, int nmax, const double* fields, void* f, const VelRec<double>* vel, const double* G,
-                       const double* Pc, int nx, int ny, int nvel, int K, int Np, hipStream_t st);
+                       const double* Pc, int nx, int ny, int nvel, int K, int Np, int stat, const double* ztab,
+                       hipStream_t st);
 hipError_t launch_stream_collide(int prec, int nmax, int waves, const SCParams& p, hipStream_t st);
 hipError_t launch_fields(int prec, const void* f, const VelRec<double>* vel, double* out, double* partials,
                          int* flag, int nx, int ny, int nvel, hipStream_t st);

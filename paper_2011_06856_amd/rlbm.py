@@ -42,6 +42,7 @@ SIGNATURES = [
     ("rlbm_get_waves", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
     ("rlbm_set_kernel", ctypes.c_int, [_vp, ctypes.c_int]),
     ("rlbm_get_kernel", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
+    ("rlbm_set_statistics", ctypes.c_int, [_vp, ctypes.c_int]),
     ("rlbm_host_feq", ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]),
     ("rlbm_host_landau", ctypes.c_int, [_dp, _dp]),
     ("rlbm_device_landau", ctypes.c_int, [ctypes.c_int, _dp, _dp]),
@@ -285,6 +286,14 @@ class Solver:
         w = ctypes.c_int()
         self._check(lib().rlbm_get_waves(self._h, ctypes.byref(w)))
         return w.value
+
+    STATISTICS = {"mj": 0, "fd": 1, "be": 2}
+
+    def set_statistics(self, name):
+        """Equilibrium statistics for the next init_fields (and host_feq):
+        "mj" Maxwell-Juttner, "fd" Fermi-Dirac, "be" Bose-Einstein."""
+        self._check(lib().rlbm_set_statistics(self._h, self.STATISTICS[name]))
+        return self
 
     KERNELS = {"auto": 0, "tile": 1, "push": 2}
 

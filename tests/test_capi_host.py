@@ -152,3 +152,26 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
         R.lib()
     with pytest.raises(ImportError, match="not built"):
         R.Solver(4, 16, 3)
+
+
+@pytest.mark.parametrize("stat,name", [(1, "fd"), (2, "be")])
+def test_host_quantum_equilibrium_matches_oracle(stat, name):
+    """The library's own radial integrals and fugacity solve (host code of
+    the kernels' device functions) against the oracle's, on the discrete
+    truncated equilibrium of Fermi-Dirac and Bose-Einstein statistics."""
+    _lib_or_skip()
+    rng = np.random.default_rng(30 + stat)
+    for (Np, K, N) in [(4, 64, 3), (6, 32, 5), (3, 12, 2)]:
+        s = R.Solver(Np, K, N).set_statistics(name)
+        q = O.Quadrature(Np, K, N)
+        for trial in range(6):
+            n, T = rng.uniform(0.1, 1.5), rng.uniform(0.6, 1.6)
+            ux, uy = rng.uniform(-0.7, 0.7, size=2)
+            if stat == 2 and n / T ** 2 >= 1.6:
+                continue
+            got = s.host_feq(n, T, ux, uy)
+            exp = q.feq(n, T, ux, uy, stat=stat)
+            np.testing.assert_allclose(got, exp, rtol=1e-12, atol=1e-13 * np.abs(exp).max())
+    s = R.Solver(3, 12, 2).set_statistics("be")
+    with pytest.raises(R.RlbmError):
+        s.host_feq(2.0, 1.0)                     # above Bose-Einstein condensation
