@@ -10,8 +10,10 @@
 set -e
 OUT=${1:-profile_out}
 export TMPDIR=/tmp
-run() {   # name, kernel, launch bytes, stats args, counter args
-    local name=$1 kernel=$2 bytes=$3 sargs=$4 cargs=$5
+SQ1="SQ_WAVES SQ_INSTS_VALU SQ_INSTS_MFMA SQ_INSTS_VMEM_RD SQ_INSTS_SMEM SQ_INSTS_SALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES"
+SQ2="SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_ANY SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_VMEM_WR SQ_WAIT_ANY SQ_INSTS_LDS SQ_ACTIVE_INST_SCA"
+run() {   # name, kernel, launch bytes, wave-velocities per launch, stats args, counter args
+    local name=$1 kernel=$2 bytes=$3 units=$4 sargs=$5 cargs=$6
     local D=$OUT/raw/$name
     timeout -s KILL 180 rocprofv3 --kernel-trace --stats -d $D/stats -o run --output-format csv -- \
         python3 -m paper_2011_06856_amd.profile_run $sargs
@@ -19,13 +21,20 @@ run() {   # name, kernel, launch bytes, stats args, counter args
         python3 -m paper_2011_06856_amd.profile_run $cargs
     timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -d $D/write -o run --output-format csv -- \
         python3 -m paper_2011_06856_amd.profile_run $cargs
+    timeout -s KILL 120 rocprofv3 --pmc $SQ1 -d $D/sq1 -o run --output-format csv -- \
+        python3 -m paper_2011_06856_amd.profile_run $cargs
+    timeout -s KILL 120 rocprofv3 --pmc $SQ2 -d $D/sq2 -o run --output-format csv -- \
+        python3 -m paper_2011_06856_amd.profile_run $cargs
     python3 -m paper_2011_06856_amd.profile_summary --stats $D/stats --fetch $D/fetch --write $D/write \
+        --sq $D/sq1 $D/sq2 --wave-units $units \
         --name $name --kernel "$kernel" --launch-bytes $bytes --out-dir $OUT \
-        --command "rocprofv3 --kernel-trace --stats -- python3 -m paper_2011_06856_amd.profile_run $sargs ; rocprofv3 --pmc FETCH_SIZE -- python3 -m paper_2011_06856_amd.profile_run $cargs ; rocprofv3 --pmc WRITE_SIZE -- python3 -m paper_2011_06856_amd.profile_run $cargs (bash paper_2011_06856_amd/profile_all.sh)"
+        --command "rocprofv3 --kernel-trace --stats -- python3 -m paper_2011_06856_amd.profile_run $sargs ; rocprofv3 --pmc FETCH_SIZE -- python3 -m paper_2011_06856_amd.profile_run $cargs ; rocprofv3 --pmc WRITE_SIZE -- python3 -m paper_2011_06856_amd.profile_run $cargs ; rocprofv3 --pmc $SQ1 -- (same) ; rocprofv3 --pmc $SQ2 -- (same) (bash paper_2011_06856_amd/profile_all.sh)"
 }
-# algorithmic bytes per launch: 8 B per site-velocity (FP32 read + write)
-run stream_collide_f32_circular_1024 "k_stream_collide<float, float, 3, 64>" 2147483648 "--steps 200" "--steps 4"
-run push_step_f32_quadrant_2048 "k_push_step<float, 5, 8, false>" 51539607552 \
+# algorithmic bytes per launch: 8 B per site-velocity (FP32 read + write);
+# wave-velocities: site-velocity updates / 64
+run stream_collide_f32_circular_1024 "k_stream_collide<float, float, 3, 64, false>" 2147483648 4194304 \
+    "--steps 200" "--steps 4"
+run push_step_f32_quadrant_2048 "k_push_step<float, 5, 8, false>" 51539607552 100663296 \
     "--workload quadrant --side 2048 --steps 20" "--workload quadrant --side 2048 --steps 3"
 
 # The 48-problem batch (FP32, the library's default work-group shape and

@@ -66,6 +66,9 @@ def main():
     ap.add_argument("--step-kernels", help="comma-separated kernel names whose launches make up one step")
     ap.add_argument("--steps", type=int, help="steps the traced run took (with --step-kernels)")
     ap.add_argument("--sv-per-step", type=float, help="site-velocity updates of one step (with --step-kernels)")
+    ap.add_argument("--sq", nargs="*", default=[], help="rocprofv3 --pmc output dirs of SQ counter passes")
+    ap.add_argument("--wave-units", type=float,
+                    help="wave-velocities per launch (site-velocity updates / 64), for per-unit SQ counts")
     a = ap.parse_args()
 
     stats = _rows(a.stats, "kernel_stats.csv")
@@ -113,6 +116,31 @@ def main():
                   "| avg launch duration | %s us |" % ("%.1f" % (avg_ns / 1e3) if avg_ns else "n/a"),
                   "| algorithmic GB/s at that duration | %s |" % ("%.0f" % (a.launch_bytes / avg_ns) if avg_ns else "n/a"),
                   ""]
+    sq = {}
+    for d in a.sq:
+        for r in _rows(d, "counter_collection.csv"):
+            if a.kernel not in r["Kernel_Name"].replace("(anonymous namespace)::", ""):
+                continue
+            sq.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    if sq:
+        avg = {k: sum(v) / len(v) for k, v in sq.items()}
+        lines += ["## Instruction mix and wave states (rocprofv3 --pmc, SQ counters, averages per launch)", "",
+                  "| counter | per launch | per wave-velocity |", "|---|---|---|"]
+        for k in sorted(avg):
+            per = ("%.2f" % (avg[k] / a.wave_units)) if (a.wave_units and k.startswith("SQ_INSTS")) else ""
+            lines.append("| %s | %.4g | %s |" % (k, avg[k], per))
+        wc = avg.get("SQ_WAVE_CYCLES")
+        if wc:
+            lines += ["", "| wave state | fraction of wave cycles |", "|---|---|"]
+            for k, label in (("SQ_WAIT_INST_ANY", "waiting on an issued instruction's result (memory counters)"),
+                             ("SQ_WAIT_ANY", "waiting on anything"),
+                             ("SQ_ACTIVE_INST_ANY", "issuing any instruction"),
+                             ("SQ_ACTIVE_INST_VALU", "issuing VALU"),
+                             ("SQ_ACTIVE_INST_SCA", "issuing scalar"),
+                             ("SQ_ACTIVE_INST_LDS", "issuing LDS")):
+                if k in avg:
+                    lines.append("| %s (%s) | %.3f |" % (k, label, avg[k] / wc))
+        lines += [""]
     if a.step_kernels and a.steps and a.sv_per_step:
         names = a.step_kernels.split(",")
         step_rows = [r for r in stats if any(k in r["Name"] for k in names)]
