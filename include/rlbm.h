@@ -46,7 +46,23 @@ enum {
     RLBM_ESTATE = -5    /* call out of order (e.g. step before init_fields) */
 };
 
-enum { RLBM_F64 = 0, RLBM_F32 = 1 };                     /* population storage */
+/* Population storage.
+ *   F64, F32   the populations f, in FP64 or FP32.
+ *   BF16DEV    the departure g = f - F of the populations from the truncated
+ *              equilibrium F of each site's last collision (Eq.
+ *              mj-feq-expansion-truncated), stored in bfloat16, with F kept as
+ *              per-shell harmonic coefficients in FP32 (Np x (2 Nm + 1) per
+ *              site, Nm = 3, 5 or 7 the order class of N): 2 bytes per
+ *              site-velocity instead of 4.  Arithmetic in FP32, Landau frame in
+ *              FP64.  Rounding g to bfloat16 each step is the only departure
+ *              from the FP32 method.
+ *   F32DEV     the same representation with g in FP32;
+ *   F64DEV     with g and the coefficients in FP64 (equal to the FP64 method up
+ *              to rounding).
+ * The deviation storages run on the push kernel (RLBM_KERNEL_PUSH) with
+ * periodic or clamped axes and Maxwell-Juttner statistics, one problem per
+ * context (not in a batch, not with the learned-form calls). */
+enum { RLBM_F64 = 0, RLBM_F32 = 1, RLBM_BF16DEV = 2, RLBM_F32DEV = 3, RLBM_F64DEV = 4 };
 /* Boundary condition per axis: what an upwind point outside the grid holds
  * (the paper's box domain states none and names boundary conditions as the
  * next step, Sec. 4):

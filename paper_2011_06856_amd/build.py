@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "librlbm.so")
-SOURCES = ["kernels.hip", "quadrature.cpp", "capi.cpp", "batch.cpp", "mlp.hip", "push.hip"]
+SOURCES = ["kernels.hip", "quadrature.cpp", "capi.cpp", "batch.cpp", "mlp.hip", "push.hip", "deviation.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions stay disabled: hipcc -O3 emits them from plain float

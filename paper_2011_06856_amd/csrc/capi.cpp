@@ -19,20 +19,21 @@ int hip_fail(rlbm_ctx c, hipError_t e, const char* where)
     return fail(c, RLBM_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-size_t elem_size(int prec) { return prec == RLBM_F64 ? 8 : (prec == RLBM_F32 ? 4 : 2); }
+size_t elem_size(int prec) { return store_size(prec); }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t f0, f1, fields, partials, flag, edges, pp0, pp1, total;
+    size_t f0, f1, fields, partials, flag, edges, pp0, pp1, cf0, cf1, total;
 };
 
 // Workspace: two population buffers, the field outputs, the per-block
 // partial charges, the non-physical flag, the initial populations of the
 // edge cells (FIXED boundaries) and the push kernel's two partial-sum
 // buffers (present whichever kernel is chosen, so that neither rlbm_step nor
-// rlbm_set_kernel allocates).
-Layout layout(int nvel, int nx, int ny, int prec)
+// rlbm_set_kernel allocates), and for deviation storage the two buffers of
+// equilibrium coefficients paired with the population buffers.
+Layout layout(int nvel, int nx, int ny, int prec, int cplanes)
 {
     const long long S = (long long)nx * ny;
     Layout L;
@@ -47,7 +48,10 @@ Layout layout(int nvel, int nx, int ny, int prec)
     L.edges = L.flag + 256;
     L.pp0 = L.edges + align256((size_t)2 * (nx + ny) * nvel * elem_size(prec));
     L.pp1 = L.pp0 + pb;
-    L.total = L.pp1 + pb;
+    const size_t cb = is_dev(prec) ? align256((size_t)cplanes * S * arith_size(prec)) : 0;
+    L.cf0 = L.pp1 + pb;
+    L.cf1 = L.cf0 + cb;
+    L.total = L.cf1 + cb;
     return L;
 }
 
@@ -61,7 +65,9 @@ void free_tables(rlbm_ctx c)
     if (c->d_Pc) (void)hipFree(c->d_Pc);
     if (c->d_corr) (void)hipFree(c->d_corr);
     if (c->d_zeta) (void)hipFree(c->d_zeta);
+    if (c->d_dz) (void)hipFree(c->d_dz);
     c->d_zeta = nullptr;
+    c->d_dz = nullptr;
     c->d_srec = nullptr; c->d_crec = nullptr; c->d_sgn = nullptr; c->d_veld = nullptr; c->d_corr = nullptr; c->d_G = nullptr; c->d_Pc = nullptr;
 }
 
@@ -116,7 +122,7 @@ int upload_tables_p(rlbm_ctx c, const std::vector<VelRec<double>>& vd, long long
 
 int upload_kernel_tables(rlbm_ctx c, const std::vector<VelRec<double>>& vd, long long S, int precision)
 {
-    if (precision == RLBM_F64) return upload_tables_p<double>(c, vd, S, precision);
+    if (arith_size(precision) == 8) return upload_tables_p<double>(c, vd, S, precision);
     return upload_tables_p<float>(c, vd, S, precision);
 }
 
@@ -134,6 +140,7 @@ bool finite_arr(const double* a, long long S)
 // WALL or FIXED axis needs the tile kernel's boundary loads.
 int resolve_kernel(rlbm_ctx c)
 {
+    if (is_dev(c->prec)) return RLBM_KERNEL_PUSH;   // deviation storage runs on the push kernel only
     if (c->kern != RLBM_KERNEL_AUTO) return c->kern;
     if (general_step(c->bcx, c->bcy, c->fstat)) return RLBM_KERNEL_TILE;
     return c->q.nvel >= RLBM_PUSH_MIN_NVEL ? RLBM_KERNEL_PUSH : RLBM_KERNEL_TILE;
@@ -194,8 +201,8 @@ int rlbm_get_quadrature(rlbm_ctx c, double* p, double* theta, double* w)
 int rlbm_workspace_bytes(rlbm_ctx c, int nx, int ny, int precision, size_t* bytes)
 {
     if (!c || !bytes || nx < 1 || ny < 1) return fail(c, RLBM_EINVAL, "workspace_bytes: bad arguments");
-    if (precision != RLBM_F64 && precision != RLBM_F32) return fail(c, RLBM_EINVAL, "unsupported precision");
-    *bytes = layout(c->q.nvel, nx, ny, precision).total;
+    if (!valid_prec(precision)) return fail(c, RLBM_EINVAL, "unsupported precision");
+    *bytes = layout(c->q.nvel, nx, ny, precision, dev_planes(c->q.Np, c->q.N)).total;
     return RLBM_OK;
 }
 
@@ -212,7 +219,10 @@ int rlbm_init_fields(rlbm_ctx c, int nx, int ny, const double* n, const double* 
         return fail(c, RLBM_EINVAL, "bad boundary condition");
     if ((bc_x == RLBM_BC_WALL || bc_y == RLBM_BC_WALL) && (c->q.K % 2))
         return fail(c, RLBM_EINVAL, "a wall needs an even number of angles (reversed velocities)");
-    if (precision != RLBM_F64 && precision != RLBM_F32) return fail(c, RLBM_EINVAL, "unsupported precision");
+    if (!valid_prec(precision)) return fail(c, RLBM_EINVAL, "unsupported precision");
+    if (is_dev(precision) && (special_bc(bc_x, bc_y) || c->stat != RLBM_STAT_MJ))
+        return fail(c, RLBM_EINVAL, "deviation storage supports periodic and clamped axes and Maxwell-Juttner "
+                                    "statistics");
     if (d_workspace && ((uintptr_t)d_workspace & 255)) return fail(c, RLBM_EINVAL, "workspace must be 256-byte aligned");
     const long long S = (long long)nx * ny;
     if (!finite_arr(n, S) || !finite_arr(T, S) || (ux && !finite_arr(ux, S)) || (uy && !finite_arr(uy, S)))
@@ -238,7 +248,7 @@ int rlbm_init_fields(rlbm_ctx c, int nx, int ny, const double* n, const double* 
     if (e != hipSuccess) return hip_fail(c, e, "hipGetDevice");
     if (scratch_setup(dev) != RLBM_OK) return fail(c, RLBM_EDEVICE, "device scratch address");
     c->dev = dev;
-    const Layout L = layout(c->q.nvel, nx, ny, precision);
+    const Layout L = layout(c->q.nvel, nx, ny, precision, dev_planes(c->q.Np, c->q.N));
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
 
     if (d_workspace) {
@@ -270,6 +280,8 @@ int rlbm_init_fields(rlbm_ctx c, int nx, int ny, const double* n, const double* 
     c->d_edges = c->ws + L.edges;
     c->pp[0] = c->ws + L.pp0;
     c->pp[1] = c->ws + L.pp1;
+    c->cf[0] = is_dev(precision) ? c->ws + L.cf0 : nullptr;
+    c->cf[1] = is_dev(precision) ? c->ws + L.cf1 : nullptr;
     c->cur = 0;
     c->pcur = 0;
     c->steps = 0;
@@ -301,6 +313,10 @@ int rlbm_init_fields(rlbm_ctx c, int nx, int ny, const double* n, const double* 
             push_free(c);
             return fail(c, prc, "push kernel tables: " + err);
         }
+        if (is_dev(precision)) {
+            const int drc = dev_setup(c, err);
+            if (drc != RLBM_OK) return fail(c, drc, "deviation tables: " + err);
+        }
     }
 
     // upload the fields and build f = f_eq
@@ -312,16 +328,21 @@ int rlbm_init_fields(rlbm_ctx c, int nx, int ny, const double* n, const double* 
     if ((e = hipMemcpyAsync(c->d_fields, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st)) != hipSuccess)
         return hip_fail(c, e, "field upload");
     if ((e = hipMemsetAsync(c->d_flag, 0, sizeof(int), st)) != hipSuccess) return hip_fail(c, e, "flag clear");
-    for (int b = 0; b < 2; ++b) {   // spare planes written by the null table entries
-        char* spare = static_cast<char*>(c->f[b]) + (size_t)c->q.nvel * S * elem_size(precision);
-        if ((e = hipMemsetAsync(spare, 0, (size_t)S * elem_size(precision), st)) != hipSuccess)
-            return hip_fail(c, e, "spare clear");
+    if (is_dev(precision)) {
+        // f = F exactly: the equilibrium's coefficients, zero deviations
+        if ((e = launch_dev_init(c, st)) != hipSuccess) return hip_fail(c, e, "deviation init kernel");
+    } else {
+        for (int b = 0; b < 2; ++b) {   // spare planes written by the null table entries
+            char* spare = static_cast<char*>(c->f[b]) + (size_t)c->q.nvel * S * elem_size(precision);
+            if ((e = hipMemsetAsync(spare, 0, (size_t)S * elem_size(precision), st)) != hipSuccess)
+                return hip_fail(c, e, "spare clear");
+        }
+        e = launch_init(precision, nmax_of(c->q.N), c->d_fields, c->f[0], c->d_veld, c->d_G, c->d_Pc, nx, ny,
+                        c->q.nvel, c->q.K, c->q.Np, c->fstat, c->d_zeta, st);
+        if (e != hipSuccess) return hip_fail(c, e, "init kernel");
+        e = launch_edges(precision, c->f[0], c->d_edges, nx, ny, c->q.nvel, st);
+        if (e != hipSuccess) return hip_fail(c, e, "edge copy kernel");
     }
-    e = launch_init(precision, nmax_of(c->q.N), c->d_fields, c->f[0], c->d_veld, c->d_G, c->d_Pc, nx, ny,
-                    c->q.nvel, c->q.K, c->q.Np, c->fstat, c->d_zeta, st);
-    if (e != hipSuccess) return hip_fail(c, e, "init kernel");
-    e = launch_edges(precision, c->f[0], c->d_edges, nx, ny, c->q.nvel, st);
-    if (e != hipSuccess) return hip_fail(c, e, "edge copy kernel");
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(c, e, "init sync");
     if (!c->ev0) {
         if ((e = hipEventCreate(&c->ev0)) != hipSuccess) return hip_fail(c, e, "event");
@@ -402,8 +423,9 @@ int rlbm_moments(rlbm_ctx c, double* n, double* eps, double* ux, double* uy, dou
 {
     if (!c) return RLBM_EINVAL;
     if (!c->have_fields) return fail(c, RLBM_ESTATE, "rlbm_moments before rlbm_init_fields");
-    hipError_t e = launch_fields(c->prec, c->f[c->cur], c->d_veld, c->d_fields, c->d_partials, c->d_flag, c->nx, c->ny,
-                                 c->q.nvel, c->st);
+    hipError_t e = is_dev(c->prec) ? launch_dev_fields(c, c->d_fields, c->d_partials, c->st)
+                                   : launch_fields(c->prec, c->f[c->cur], c->d_veld, c->d_fields, c->d_partials,
+                                                   c->d_flag, c->nx, c->ny, c->q.nvel, c->st);
     if (e != hipSuccess) return hip_fail(c, e, "fields launch");
     return fields_out(c, n, eps, ux, uy, charges);
 }
@@ -419,8 +441,14 @@ int rlbm_moments_device(rlbm_ctx c, double* d_fields, double* d_charges)
                                         std::to_string(scratch_max_sites()) + " sites)");
     double* partials = static_cast<double*>(scratch_ptr(c->dev));
     if (!partials) return fail(c, RLBM_ESTATE, "device scratch not set up");
-    const hipError_t e = launch_fields_charges(c->prec, c->f[c->cur], c->d_veld, d_fields ? d_fields : c->d_fields,
-                                               partials, d_charges, c->d_flag, c->nx, c->ny, c->q.nvel, c->st);
+    hipError_t e;
+    if (is_dev(c->prec)) {
+        e = launch_dev_fields(c, d_fields ? d_fields : c->d_fields, partials, c->st);
+        if (e == hipSuccess && d_charges) e = launch_charges_sum(partials, fields_blocks(c->S), d_charges, c->st);
+    } else {
+        e = launch_fields_charges(c->prec, c->f[c->cur], c->d_veld, d_fields ? d_fields : c->d_fields, partials,
+                                  d_charges, c->d_flag, c->nx, c->ny, c->q.nvel, c->st);
+    }
     return e == hipSuccess ? RLBM_OK : hip_fail(c, e, "moments_device launch");
 }
 
@@ -467,6 +495,7 @@ int rlbm_populations_bytes(rlbm_ctx c, size_t* bytes)
     if (!c || !bytes) return RLBM_EINVAL;
     if (!c->have_fields) return fail(c, RLBM_ESTATE, "no populations yet");
     *bytes = (size_t)c->q.nvel * c->S * elem_size(c->prec);
+    if (is_dev(c->prec)) *bytes += (size_t)dev_planes(c->q.Np, c->q.N) * c->S * arith_size(c->prec);
     return RLBM_OK;
 }
 
@@ -477,7 +506,10 @@ int rlbm_get_populations(rlbm_ctx c, void* host, size_t bytes)
     if (rc != RLBM_OK) return rc;
     if (!host || bytes != need) return fail(c, RLBM_EINVAL, "population buffer size mismatch");
     hipError_t e = hipStreamSynchronize(c->st);
-    if (e == hipSuccess) e = hipMemcpy(host, c->f[c->cur], need, hipMemcpyDeviceToHost);
+    const size_t gb = (size_t)c->q.nvel * c->S * elem_size(c->prec);
+    if (e == hipSuccess) e = hipMemcpy(host, c->f[c->cur], gb, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && is_dev(c->prec))
+        e = hipMemcpy(static_cast<char*>(host) + gb, c->cf[c->cur], need - gb, hipMemcpyDeviceToHost);
     return e == hipSuccess ? RLBM_OK : hip_fail(c, e, "get_populations");
 }
 
@@ -488,7 +520,10 @@ int rlbm_set_populations(rlbm_ctx c, const void* host, size_t bytes)
     if (rc != RLBM_OK) return rc;
     if (!host || bytes != need) return fail(c, RLBM_EINVAL, "population buffer size mismatch");
     hipError_t e = hipStreamSynchronize(c->st);
-    if (e == hipSuccess) e = hipMemcpy(c->f[c->cur], host, need, hipMemcpyHostToDevice);
+    const size_t gb = (size_t)c->q.nvel * c->S * elem_size(c->prec);
+    if (e == hipSuccess) e = hipMemcpy(c->f[c->cur], host, gb, hipMemcpyHostToDevice);
+    if (e == hipSuccess && is_dev(c->prec))
+        e = hipMemcpy(c->cf[c->cur], static_cast<const char*>(host) + gb, need - gb, hipMemcpyHostToDevice);
     c->pvalid = 0;
     return e == hipSuccess ? RLBM_OK : hip_fail(c, e, "set_populations");
 }
@@ -500,6 +535,8 @@ int rlbm_set_kernel(rlbm_ctx c, int kind)
         return fail(c, RLBM_EINVAL, "unknown kernel kind");
     if (kind == RLBM_KERNEL_PUSH && c->have_fields && general_step(c->bcx, c->bcy, c->fstat))
         return fail(c, RLBM_EINVAL, "walls, fixed edges and quantum statistics need the tile kernel");
+    if (kind == RLBM_KERNEL_TILE && c->have_fields && is_dev(c->prec))
+        return fail(c, RLBM_EINVAL, "deviation storage runs on the push kernel");
     c->kern = kind;
     c->pvalid = 0;
     return RLBM_OK;

@@ -843,6 +843,12 @@ hipError_t launch_fields_charges(int prec, const void* f, const VelRec<double>* 
     return hipGetLastError();
 }
 
+hipError_t launch_charges_sum(const double* partials, int nb, double* charges, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_charges_sum, dim3(1), dim3(256), 0, st, partials, nb, charges);
+    return hipGetLastError();
+}
+
 namespace {
 __global__ void k_landau_probe(const double* __restrict__ mom, double* __restrict__ out, int count)
 {

@@ -29,6 +29,24 @@
 // weights are ax = dt sx cos, ay = dt sy sin and the moment rows are p^a
 // times {1, cos, sin, cos^2, cos sin}, so the 32 weighted moment sums of a
 // segment follow from 9 angular monomial sums of f (9 FMAs per velocity).
+//
+// Deviation storage (DEV): a site stores g_v = f_v - F_v, with F the
+// truncated equilibrium (Eq. mj-feq-expansion-truncated) its last collision
+// produced, kept as per-shell harmonic coefficients C (F_v = sum_t C_t H_t(v),
+// H_t = w_v {1, cos m th, sin m th}).  The streamed population is
+//   f*_v(x) = sum_c w_c(v) g_v(x_c) + E_v(x),
+//   E_v(x)  = sum_c w_c(v) F_v(x_c)   (corners x_c of Eq. interpolation).
+// Inside a segment w_c are the bilinear monomials of ax = dt sx cos th and
+// ay = dt sy sin th, so E_v / w_v is itself a harmonic series of order N + 2
+// in th, whose coefficients follow from the four corners' C by the product
+// rules of cos th, sin th and cos th sin th with the harmonics.  The
+// collision then gives
+//   g_new = f_new - F_new = (1 - omega_v) (f*_v - F_new,v),
+// i.e. per velocity the bilinear sum of g plus one series of 2N + 5 terms
+// (E - F_new, formed once per segment), and the stored deviation is rounded
+// to the storage type (bfloat16: half the bytes of FP32).  The pushed partial
+// sums hold the moments of the full f_new = g_new + F_new: the F part of a
+// segment's monomial sums is sum_t C_t Y_t with per-segment tables Y.
 #include <cstring>
 #include <new>
 #include <type_traits>
@@ -56,18 +74,61 @@ struct alignas(16) PAddr {
 };
 // arithmetic record
 //   w[4]     bilinear weights (1-ax)(1-ay), ax(1-ay), (1-ax)ay, ax ay
-//   H[]      w_v {1, cos th, sin th, ..., cos NM th, sin NM th}
+//   H[NH]    w_v {1, cos th, sin th, ..., cos m th, sin m th}: m up to NM
+//            (NH = 2 NM + 1), or NM + 2 for deviation storage (NH = 2 NM + 5)
 //   cth sth  direction (collision frequency U^0 - U.n_v)
 //   mono[8]  c, s, c^2, c s, c^3, c^2 s, c^3 s, c^2 s^2 with c = cos th, s = sin th
 //   woff     byte offset of the velocity's output plane (padding: the spare plane)
-template <typename T, int NM>
+template <typename T, int NH>
 struct alignas(16) PRec {
     T w[4];
-    T H[2 * NM + 1];
+    T H[NH];
     T cth, sth;
     T mono[8];
     long long woff;
 };
+
+// Harmonic entries of a record: the own-site equilibrium (order NM), or the
+// deviation form's corner series (order NM + 2).
+__host__ __device__ constexpr int push_nh(int NM, bool dev) { return 2 * NM + 1 + (dev ? 4 : 0); }
+
+// Storage of the populations (plain) or deviations (DEV) and its conversion
+// to the arithmetic type: FP64, FP32, or bfloat16 (the high half of the FP32
+// pattern; rounding to nearest even).
+template <typename T, typename ST>
+__device__ __forceinline__ T st_to(ST s) { return (T)s; }
+template <>
+__device__ __forceinline__ float st_to<float, unsigned short>(unsigned short s)
+{
+    return __uint_as_float((unsigned)s << 16);
+}
+// Rounding to the storage type.  bfloat16 rounds stochastically: round to
+// nearest would drop every per-step change of a deviation smaller than half
+// a bfloat16 ulp, the same way each step (a bias that accumulates), while
+// stochastic rounding rounds up with probability equal to the discarded
+// fraction, so the stored value is exact in expectation.  r: 32 random bits.
+template <typename ST, typename T>
+__device__ __forceinline__ ST to_st(T v, unsigned r) { return (ST)v; }
+template <>
+__device__ __forceinline__ unsigned short to_st<unsigned short, float>(float v, unsigned r)
+{
+    // v_cvt_sr_bf16_f32 adds the high 16 bits of r to the 16 discarded bits
+    // and truncates; the result is a bfloat16 pair (low half written here)
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    const b2 z = {};
+    return __builtin_bit_cast(unsigned short, __builtin_amdgcn_cvt_sr_bf16_f32(z, v, r, false)[0]);
+}
+
+// 32-bit finaliser of MurmurHash3 (Appleby): a bijective mix of the bits.
+__device__ __forceinline__ unsigned fmix32(unsigned h)
+{
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
 
 // One segment: the velocities of shell i with upwind signs (sx, sy) of
 // quadrant q, padded with null records to whole load batches.
@@ -78,8 +139,11 @@ struct PSeg {
 
 struct PushParams {
     const PAddr* paddr;      // PAddr[]
-    const void* prec;        // PRec<T, NM>[]
+    const void* prec;        // PRec<T, NH>[]
     const PSeg* seg;         // [4][Np]
+    const void* ytab;        // deviation storage: [4][Np][2 NM + 1][9] (T), Y[q][i][t][j] = sum over the
+                             // segment's velocities of H_t mono_j, mono = (1, c, s, c^2, c s, c^3, c^2 s,
+                             // c^3 s, c^2 s^2); null otherwise
     const double* G;
     const double* Pc;
     int nx, ny, Np, bcx, bcy, ntiles;
@@ -151,26 +215,86 @@ __host__ __device__ inline long long halo_off(long long S, int edge, int dir, in
     return 3LL * NMOM * S + ((((long long)(edge * 2 + dir) * 3 + d) * NMOM + k) * ny + row) * ntx + tc;
 }
 
+// Corner series of the deviation form for one segment (upwind signs sx, sy):
+// the harmonic coefficients De[0 .. 2 NM + 4] of
+//   E(th) / w = A0 + al c A^x + be s A^y + al be c s A^xy,
+// al = dt sx, be = dt sy, c = cos th, s = sin th, where A0 = C(x0), A^x =
+// C(x1) - C(x0), A^y = C(x2) - C(x0), A^xy = C(x3) - C(x1) - C(x2) + C(x0) are
+// the bilinear-monomial combinations of the corner coefficients (x1 the x
+// upwind neighbour, x2 the y upwind one, x3 both).  Products with c, s and
+// c s = sin(2 th) / 2 move a harmonic m to m +- 1 and m +- 2.  Index of
+// cos m th: 2m - 1, of sin m th: 2m (m >= 1), constant: 0.
+// AT: the arithmetic type (that of the step).
+template <int NM, typename AT, typename LoadC>
+__device__ __forceinline__ void corner_series(AT al, AT be, LoadC loadc, AT* De)
+{
+    constexpr int NT = 2 * NM + 1, NE = NT + 4;
+#pragma unroll
+    for (int t = 0; t < NE; ++t) De[t] = AT(0);
+    auto ic = [](int k) { return k == 0 ? 0 : 2 * k - 1; };
+    auto is = [](int k) { return 2 * k; };
+    const AT hal = AT(0.5) * al, hbe = AT(0.5) * be, qab = AT(0.25) * al * be;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        AT c0, c1, c2, c3;
+        loadc(t, c0, c1, c2, c3);
+        const AT A0 = c0, Ax = c1 - c0, Ay = c2 - c0, Axy = (c3 - c1) - (c2 - c0);
+        const AT h = hal * Ax, k = hbe * Ay, l = qab * Axy;
+        if (t == 0) {
+            De[0] += A0;
+            De[ic(1)] += AT(2) * h;
+            De[is(1)] += AT(2) * k;
+            De[is(2)] += AT(2) * l;
+        } else if (t & 1) {   // cos m th
+            const int m = (t + 1) / 2;
+            De[ic(m)] += A0;
+            De[ic(m + 1)] += h;
+            De[ic(m - 1)] += h;
+            De[is(m + 1)] += k;
+            if (m >= 2) De[is(m - 1)] -= k;
+            De[is(m + 2)] += l;
+            if (m >= 3) De[is(m - 2)] -= l;
+            if (m == 1) De[is(1)] += l;
+        } else {              // sin m th
+            const int m = t / 2;
+            De[is(m)] += A0;
+            De[is(m + 1)] += h;
+            if (m >= 2) De[is(m - 1)] += h;
+            De[ic(m - 1)] += k;
+            De[ic(m + 1)] -= k;
+            De[ic(m + 2)] -= l;
+            if (m >= 2) De[ic(m - 2)] += l;
+            if (m == 1) De[ic(1)] += l;
+        }
+    }
+}
+
 // One wave-tile: 64 sites of row ty starting at column 64 tx.  INIT computes
 // only the partial sums of the current populations (no stream, no
 // collision, no population store).  lh: this wave's LDS, the 96-entry halo
 // accumulator [edge][dir][d][k] followed by the row slots [d][k][64].
-template <typename T, int NM, int LB, bool INIT>
-__device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restrict__ fout, const T* __restrict__ pin,
-                                          T* __restrict__ pout, const PushParams& P, int tile, T* __restrict__ lh,
-                                          bool live)
+// T is the arithmetic type, ST the storage type of the populations (plain)
+// or of the deviations (DEV, with the per-shell equilibrium coefficients in
+// cin / cout, [Np][2 NM + 1][S] of T).
+template <typename T, typename ST, int NM, int LB, bool INIT, bool DEV>
+__device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __restrict__ fout, const T* __restrict__ pin,
+                                          T* __restrict__ pout, const T* __restrict__ cin, T* __restrict__ cout,
+                                          const PushParams& P, int tile, T* __restrict__ lh, bool live)
 {
     constexpr int NT = 2 * NM + 1;
+    constexpr int NH = push_nh(NM, DEV);
     constexpr int GS = (RLBM_NMAX + 1) * (RLBM_NMAX + 1);
-    using CRec = const PUSH_CONST_AS PRec<T, NM>;
+    using CRec = const PUSH_CONST_AS PRec<T, NH>;
     using CAddr = const PUSH_CONST_AS PAddr;
     CAddr* const adr = (CAddr*)P.paddr;
     using CSeg = const PUSH_CONST_AS PSeg;
     using CDbl = const PUSH_CONST_AS double;
+    using CTab = const PUSH_CONST_AS T;
     CRec* const rec = (CRec*)P.prec;
     CSeg* const seg = (CSeg*)P.seg;
     CDbl* const Gtab = (CDbl*)P.G;
     CDbl* const Pc = (CDbl*)P.Pc;
+    CTab* const ytab = (CTab*)P.ytab;
 
     const int lane = threadIdx.x & 63;
     const int ntx = (P.nx + 63) >> 6;
@@ -191,9 +315,12 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
     //    pushed by the previous step: the three row slots at this column, and
     //    for the first / last column of the tile the halo parts of the
     //    upwind column outside it (FP64 sums)
-    T a0 = T(0), ax = T(0), ay = T(0);
+    //    Collision factors: plain, omega = a0 - ax cos - ay sin; DEV,
+    //    1 - omega = a0 + ax cos + ay sin.
+    T a0 = DEV ? T(1) : T(0), ax = T(0), ay = T(0);
     double fn_ = 0, fT = 0, fU0 = 0, fUx = 0, fUy = 0;
     int ok = 0;
+    unsigned srseed = 0;
     if (!INIT) {
         const int cl = wrapi(tx * 64 - 1, P.nx, P.bcx);            // column left of the tile
         const int cr = wrapi(tx * 64 + last + 1, P.nx, P.bcx);     // column right of the tile
@@ -218,13 +345,28 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
         const Frame fr = landau_frame(mom);
         ok = fr.ok;
         if (!fr.ok && active) atomicOr(P.flag, 1);
-        a0 = fr.ok ? (T)(P.rate * fr.U0) : T(0);
-        ax = fr.ok ? (T)(P.rate * fr.Ux) : T(0);
-        ay = fr.ok ? (T)(P.rate * fr.Uy) : T(0);
+        if (DEV) {
+            a0 = fr.ok ? (T)(1.0 - P.rate * fr.U0) : T(1);
+            ax = fr.ok ? (T)(P.rate * fr.Ux) : T(0);
+            ay = fr.ok ? (T)(P.rate * fr.Uy) : T(0);
+        } else {
+            a0 = fr.ok ? (T)(P.rate * fr.U0) : T(0);
+            ax = fr.ok ? (T)(P.rate * fr.Ux) : T(0);
+            ay = fr.ok ? (T)(P.rate * fr.Uy) : T(0);
+        }
         fn_ = fr.n; fT = fr.T; fU0 = fr.U0; fUx = fr.Ux; fUy = fr.Uy;
+        // stochastic rounding (bfloat16 deviations): a random stream per site
+        // and step drawn from the site index and the bits of its moments,
+        // which change from step to step; deterministic in the stored state,
+        // so that a resumed run or a replayed graph rounds alike
+        if (DEV && sizeof(ST) == 2) {
+            const unsigned long long b0 = __double_as_longlong(mom[0]), b3 = __double_as_longlong(mom[3]);
+            srseed = fmix32((unsigned)site * 0x9e3779b9u ^ (unsigned)b0 ^ (unsigned)(b0 >> 32) ^
+                            fmix32((unsigned)b3 ^ (unsigned)(b3 >> 32)));
+        }
     }
 
-    constexpr unsigned ES = sizeof(T);
+    constexpr unsigned ES = sizeof(ST);
     const unsigned ocb = (unsigned)xc * ES;
     const unsigned omb = (unsigned)xm * ES;
     const unsigned opb = (unsigned)xp * ES;
@@ -234,7 +376,7 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
     const char* const inb = reinterpret_cast<const char*>(fin) + rowb;
     char* const outb = reinterpret_cast<char*>(fout) + rowb;
     auto ld = [](const char* base, unsigned off) __attribute__((always_inline)) -> T {
-        return *reinterpret_cast<const T*>(base + off);
+        return st_to<T, ST>(*reinterpret_cast<const ST*>(base + off));
     };
     const T act = active ? T(1) : T(0);   // columns past the grid contribute nothing
     // value of lane (lane - sx), zero where that lane is outside the wave
@@ -261,6 +403,9 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
     auto run = [&](auto fast) __attribute__((always_inline)) {
         constexpr bool FAST = decltype(fast)::value;
         for (int i = 0; i < P.Np; ++i) {
+            // plain: the new equilibrium's coefficients; DEV: the stored
+            // (rounded) coefficients of the new equilibrium, or in INIT those
+            // of the current state
             T cc[NT];
             if (!INIT) {
                 shell_coeffs<NM>(Gtab + (size_t)i * GS, Pc, fn_, fT, fU0, fUx, fUy,
@@ -273,12 +418,36 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
                                          cc[2 * mm] = (T)sm;
                                      }
                                  });
+                if (DEV && (FAST || active)) {
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) cout[(long long)(i * NT + t) * S + site] = cc[t];
+                }
+            } else if (DEV) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) cc[t] = cin[(long long)(i * NT + t) * S + site];
             }
 #pragma unroll 1
             for (int q = 0; q < 4; ++q) {
                 const int sx = qsx(q), sy = qsy(q);
                 const int dY = sy > 0 ? 1 : 2;   // row slot of the y-displaced parts
                 CSeg& G = seg[q * P.Np + i];
+                // DEV: the segment's series E - F_new (E from the corners' old
+                // coefficients)
+                T D[DEV ? NH : 1];
+                if (DEV && !INIT) {
+                    const int xs = sx > 0 ? xm : xp;
+                    const int ys = sy > 0 ? ym : yp;
+                    const long long s0 = site, s1 = (long long)ty * P.nx + xs, s2 = (long long)ys * P.nx + xc,
+                                    s3 = (long long)ys * P.nx + xs;
+                    corner_series<NM, T>(dt * (T)sx, dt * (T)sy,
+                                         [&](int t, T& c0, T& c1, T& c2, T& c3) __attribute__((always_inline)) {
+                                             const T* pl = cin + (long long)(i * NT + t) * S;
+                                             c0 = pl[s0]; c1 = pl[s1]; c2 = pl[s2]; c3 = pl[s3];
+                                         },
+                                         D);
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) D[t] -= cc[t];
+                }
                 T Sm[9];   // sum f, f c, f s, f c^2, f c s, f c^3, f c^2 s, f c^3 s, f c^2 s^2
 #pragma unroll
                 for (int j = 0; j < 9; ++j) Sm[j] = T(0);
@@ -292,7 +461,7 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
                         const int ahead = min(v0 + (kb + RLBM_PUSH_PREFETCH) * LB, P.nrec - LB);
                         using CWord = const PUSH_CONST_AS unsigned;
                         const PUSH_CONST_AS char* rb = (const PUSH_CONST_AS char*)(rec + ahead);
-                        constexpr int RB = LB * (int)sizeof(PRec<T, NM>);
+                        constexpr int RB = LB * (int)sizeof(PRec<T, NH>);
 #pragma unroll
                         for (int o = 0; o < RB; o += 64) pf += *(CWord*)(rb + o);
                         pf += *(CWord*)(rb + RB - 4);
@@ -326,6 +495,20 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
                             // padding records (zero equilibrium row) contribute
                             // nothing; real ones exactly their value, as in the step
                             fnew = Rr.H[0] != T(0) ? raw[b][0] : T(0);
+                        } else if (DEV) {
+                            const T gs = Rr.w[0] * raw[b][0] + Rr.w[1] * raw[b][1] + Rr.w[2] * raw[b][2] +
+                                         Rr.w[3] * raw[b][3];
+                            T dv = D[0] * Rr.H[0];
+#pragma unroll
+                            for (int t = 1; t < NH; ++t) dv += D[t] * Rr.H[t];
+                            const T om1 = a0 + ax * Rr.cth + ay * Rr.sth;
+                            // velocity v draws srseed + v phi (a Weyl sequence, phi
+                            // the golden-ratio increment)
+                            const unsigned rv = srseed + (unsigned)(v0 + kb * LB + b) * 0x9e3779b9u;
+                            const ST gq = to_st<ST, T>(om1 * (gs + dv), rv);
+                            fnew = st_to<T, ST>(gq);   // the stored value feeds the partial sums
+                            ST* dst = reinterpret_cast<ST*>(outb + Rr.woff + ocb);
+                            if (FAST || active) __builtin_nontemporal_store(gq, dst);
                         } else {
                             const T f = Rr.w[0] * raw[b][0] + Rr.w[1] * raw[b][1] + Rr.w[2] * raw[b][2] +
                                         Rr.w[3] * raw[b][3];
@@ -345,6 +528,19 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
                         for (int j = 0; j < 8; ++j) Sm[1 + j] = fma(fnew, (T)Rr.mono[j], Sm[1 + j]);
                     }
                     if (RLBM_PUSH_PREFETCH > 0) asm volatile("" ::"s"(pf));
+                }
+                // DEV: add the monomial sums of the equilibrium part F of the
+                // stored state, sum_t C_t Y_t (explicit FMAs, same order in
+                // the step and the rebuild)
+                if (DEV) {
+                    CTab* yq = ytab + (size_t)(q * P.Np + i) * NT * 9;
+#pragma unroll
+                    for (int j = 0; j < 9; ++j) {
+                        T acc = Sm[j];
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) acc = fma(cc[t], (T)yq[t * 9 + j], acc);
+                        Sm[j] = acc;
+                    }
                 }
                 // fold the monomial sums into the weighted moment sums of the
                 // segment's four corners: with T_e = sum f e, the corner sums
@@ -425,9 +621,10 @@ __device__ __forceinline__ void push_tile(const T* __restrict__ fin, T* __restri
 #define RLBM_PUSH_LB_F32 8
 #endif
 
-template <typename T, int NM, int LB, bool INIT>
-__global__ __launch_bounds__(256, RLBM_PUSH_WPE) void k_push_step(const T* __restrict__ fin, T* __restrict__ fout,
-                                                   const T* __restrict__ pin, T* __restrict__ pout, PushParams P)
+template <typename T, typename ST, int NM, int LB, bool INIT, bool DEV>
+__global__ __launch_bounds__(256, RLBM_PUSH_WPE) void k_push_step(const ST* __restrict__ fin, ST* __restrict__ fout,
+                                                   const T* __restrict__ pin, T* __restrict__ pout,
+                                                   const T* __restrict__ cin, T* __restrict__ cout, PushParams P)
 {
     extern __shared__ __align__(16) unsigned char psmem[];
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave-uniform
@@ -444,7 +641,7 @@ __global__ __launch_bounds__(256, RLBM_PUSH_WPE) void k_push_step(const T* __res
     const bool live = true;
     const int tile = ty * ntx + col;
     T* lh = reinterpret_cast<T*>(psmem) + (size_t)wv * (96 + 3 * NMOM * 64);
-    push_tile<T, NM, LB, INIT>(fin, fout, pin, pout, P, tile, lh, live);
+    push_tile<T, ST, NM, LB, INIT, DEV>(fin, fout, pin, pout, cin, cout, P, tile, lh, live);
 }
 
 // Batched form: the push-kernel problems of a batch advance together in one
@@ -480,9 +677,9 @@ __global__ __launch_bounds__(256, RLBM_PUSH_WPE) void k_push_batch(const PushDes
     if (ty >= P.ny) return;   // whole waves; the kernel has no barrier
     const int tile = ty * ntx + col;
     T* lh = reinterpret_cast<T*>(psmem) + (size_t)wv * (96 + 3 * NMOM * 64);
-    push_tile<T, NM, LB, false>(static_cast<const T*>(D.f[parity]), static_cast<T*>(D.f[parity ^ 1]),
-                                static_cast<const T*>(D.pp[parity]), static_cast<T*>(D.pp[parity ^ 1]), P, tile, lh,
-                                true);
+    push_tile<T, T, NM, LB, false, false>(static_cast<const T*>(D.f[parity]), static_cast<T*>(D.f[parity ^ 1]),
+                                          static_cast<const T*>(D.pp[parity]), static_cast<T*>(D.pp[parity ^ 1]),
+                                          nullptr, nullptr, P, tile, lh, true);
 }
 
 // Load batch per precision: FP64 holds half as many values per register.
@@ -491,19 +688,19 @@ struct PushLB {
     static constexpr int value = sizeof(T) == 8 ? 4 : RLBM_PUSH_LB_F32;
 };
 
-template <typename T, int NM>
-hipError_t launch_push_t(bool init, const void* fin, void* fout, const void* pin, void* pout, const PushParams& P,
-                         hipStream_t st)
+template <typename T, typename ST, int NM, bool DEV>
+hipError_t launch_push_t(bool init, const void* fin, void* fout, const void* pin, void* pout, const void* cin,
+                         void* cout, const PushParams& P, hipStream_t st)
 {
     constexpr int LB = PushLB<T>::value;
     const unsigned blocks = (unsigned)(((P.nx + 63) / 64) * ((P.ny + 3) / 4));
     const size_t lds = (size_t)4 * (96 + 3 * NMOM * 64) * sizeof(T);   // 4 waves x (halo + row slots)
     if (init)
-        hipLaunchKernelGGL((k_push_step<T, NM, LB, true>), dim3(blocks), dim3(256), lds, st, (const T*)fin, (T*)fout,
-                           (const T*)pin, (T*)pout, P);
+        hipLaunchKernelGGL((k_push_step<T, ST, NM, LB, true, DEV>), dim3(blocks), dim3(256), lds, st,
+                           (const ST*)fin, (ST*)fout, (const T*)pin, (T*)pout, (const T*)cin, (T*)cout, P);
     else
-        hipLaunchKernelGGL((k_push_step<T, NM, LB, false>), dim3(blocks), dim3(256), lds, st, (const T*)fin, (T*)fout,
-                           (const T*)pin, (T*)pout, P);
+        hipLaunchKernelGGL((k_push_step<T, ST, NM, LB, false, DEV>), dim3(blocks), dim3(256), lds, st,
+                           (const ST*)fin, (ST*)fout, (const T*)pin, (T*)pout, (const T*)cin, (T*)cout, P);
     return hipGetLastError();
 }
 
@@ -517,19 +714,26 @@ hipError_t launch_push_batch_t(const void* descs, int nprob, int wgs, int parity
     return hipGetLastError();
 }
 
-template <typename T, int NM>
-int upload_push_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, int precision, std::string& err)
+// Tables of the push kernel: segment-ordered records (T arithmetic, ST
+// storage), and for deviation storage the per-segment monomial sums Y of
+// the equilibrium basis.
+template <typename T, typename ST, int NM, bool DEV>
+int upload_push_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, std::string& err)
 {
     constexpr int LB = PushLB<T>::value;
+    constexpr int NT = 2 * NM + 1;
+    constexpr int NH = push_nh(NM, DEV);
     const int Np = c->q.Np, K = c->q.K, nv = c->q.nvel;
-    const long long S = c->S, es = (long long)sizeof(T);
-    std::vector<PRec<T, NM>> recs;
+    const long long S = c->S, es = (long long)sizeof(ST);
+    std::vector<PRec<T, NH>> recs;
     std::vector<PAddr> adrs;
     std::vector<PSeg> segs(4 * (size_t)Np);
+    std::vector<T> ytab;
+    if (DEV) ytab.assign((size_t)4 * Np * NT * 9, T(0));
     // padding records: zero weights and equilibrium row, a store to the
     // spare plane, loads from the plane of the record before them (cache
     // hits, no extra HBM reads)
-    PRec<T, NM> null;
+    PRec<T, NH> null;
     std::memset(&null, 0, sizeof(null));
     null.woff = (long long)nv * S * es;
     for (int q = 0; q < 4; ++q)
@@ -538,19 +742,31 @@ int upload_push_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, int precisi
             G.begin = (int)recs.size();
             G.p = c->q.shell_p[i];
             int count = 0;
+            double Y[NT][9] = {};
             for (int j = 0; j < K; ++j) {
                 const int v = i * K + j;
                 const VelRec<double>& R = vd[v];
                 if ((int)R.sx != qsx(q) || (int)R.sy != qsy(q)) continue;
-                PRec<T, NM> A;
+                PRec<T, NH> A;
                 std::memset(&A, 0, sizeof(A));
                 A.w[0] = (T)R.w00; A.w[1] = (T)R.w10; A.w[2] = (T)R.w01; A.w[3] = (T)R.w11;
-                for (int t = 0; t < 2 * NM + 1; ++t) A.H[t] = (T)R.H[t];
+                // harmonics w {1, cos m th, sin m th}: up to the expansion
+                // order (the equilibrium), or two beyond it (the corner series)
+                const int mtop = DEV ? c->q.N + 2 : c->q.N;
+                double H[NH] = {};
+                H[0] = c->q.w[v];
+                for (int m = 1; 2 * m < NH && m <= mtop; ++m) {
+                    H[2 * m - 1] = c->q.w[v] * std::cos(m * c->q.theta[v]);
+                    H[2 * m] = c->q.w[v] * std::sin(m * c->q.theta[v]);
+                }
+                for (int t = 0; t < NH; ++t) A.H[t] = (T)H[t];
                 const double cs = R.cth, sn = R.sth;
                 A.cth = (T)cs; A.sth = (T)sn;
-                const double mono[8] = {cs, sn, cs * cs, cs * sn, cs * cs * cs, cs * cs * sn, cs * cs * cs * sn,
+                const double mono[9] = {1.0, cs, sn, cs * cs, cs * sn, cs * cs * cs, cs * cs * sn, cs * cs * cs * sn,
                                         cs * cs * sn * sn};
-                for (int t = 0; t < 8; ++t) A.mono[t] = (T)mono[t];
+                for (int t = 0; t < 8; ++t) A.mono[t] = (T)mono[t + 1];
+                for (int t = 0; t < NT; ++t)
+                    for (int k = 0; k < 9; ++k) Y[t][k] += R.H[t] * mono[k];
                 A.woff = (long long)v * S * es;
                 PAddr D;
                 std::memset(&D, 0, sizeof(D));
@@ -561,6 +777,9 @@ int upload_push_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, int precisi
                 adrs.push_back(D);
                 ++count;
             }
+            if (DEV)
+                for (int t = 0; t < NT; ++t)
+                    for (int k = 0; k < 9; ++k) ytab[((size_t)(q * Np + i) * NT + t) * 9 + k] = (T)Y[t][k];
             while (count % LB) {
                 PAddr nulla;
                 std::memset(&nulla, 0, sizeof(nulla));
@@ -582,19 +801,25 @@ int upload_push_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, int precisi
     }
     c->pnrec = (int)recs.size();
     hipError_t e;
-    if ((e = hipMalloc(&c->d_prec, recs.size() * sizeof(PRec<T, NM>))) != hipSuccess) return RLBM_ENOMEM;
+    if ((e = hipMalloc(&c->d_prec, recs.size() * sizeof(PRec<T, NH>))) != hipSuccess) return RLBM_ENOMEM;
     if ((e = hipMalloc(&c->d_paddr, adrs.size() * sizeof(PAddr))) != hipSuccess) return RLBM_ENOMEM;
     if ((e = hipMemcpy(c->d_paddr, adrs.data(), adrs.size() * sizeof(PAddr), hipMemcpyHostToDevice)) != hipSuccess) {
         err = hipGetErrorString(e);
         return RLBM_EDEVICE;
     }
     if ((e = hipMalloc((void**)&c->d_pseg, segs.size() * sizeof(PSeg))) != hipSuccess) return RLBM_ENOMEM;
-    if ((e = hipMemcpy(c->d_prec, recs.data(), recs.size() * sizeof(PRec<T, NM>), hipMemcpyHostToDevice)) != hipSuccess ||
+    if ((e = hipMemcpy(c->d_prec, recs.data(), recs.size() * sizeof(PRec<T, NH>), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d_pseg, segs.data(), segs.size() * sizeof(PSeg), hipMemcpyHostToDevice)) != hipSuccess) {
         err = hipGetErrorString(e);
         return RLBM_EDEVICE;
     }
-    (void)precision;
+    if (DEV) {
+        if ((e = hipMalloc(&c->d_pytab, ytab.size() * sizeof(T))) != hipSuccess) return RLBM_ENOMEM;
+        if ((e = hipMemcpy(c->d_pytab, ytab.data(), ytab.size() * sizeof(T), hipMemcpyHostToDevice)) != hipSuccess) {
+            err = hipGetErrorString(e);
+            return RLBM_EDEVICE;
+        }
+    }
     return RLBM_OK;
 }
 
@@ -605,7 +830,7 @@ int upload_push_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, int precisi
 // (2 edges x 2 directions x 3 rows x 8 moments per tile and row).
 size_t push_partial_bytes(int prec, int nx, int ny)
 {
-    const size_t es = prec == RLBM_F64 ? 8 : 4;
+    const size_t es = arith_size(prec);
     const size_t ntx = (size_t)(nx + 63) / 64;
     return ((size_t)3 * NMOM * nx * ny + (size_t)2 * 2 * 3 * NMOM * ny * ntx) * es;
 }
@@ -618,11 +843,25 @@ void push_free(rlbm_ctx c)
     if (c->d_prec) (void)hipFree(c->d_prec);
     if (c->d_paddr) (void)hipFree(c->d_paddr);
     if (c->d_pseg) (void)hipFree(c->d_pseg);
+    if (c->d_pytab) (void)hipFree(c->d_pytab);
     c->d_prec = nullptr;
     c->d_paddr = nullptr;
     c->d_pseg = nullptr;
+    c->d_pytab = nullptr;
     c->pvalid = 0;
 }
+
+namespace {
+template <typename T, typename ST, bool DEV>
+int push_setup_n(rlbm_ctx c, const std::vector<VelRec<double>>& vd, std::string& err)
+{
+    switch (nmax_of(c->q.N)) {
+        case 3: return upload_push_t<T, ST, 3, DEV>(c, vd, err);
+        case 5: return upload_push_t<T, ST, 5, DEV>(c, vd, err);
+        default: return upload_push_t<T, ST, 7, DEV>(c, vd, err);
+    }
+}
+}  // namespace
 
 // Build the push tables for the context's grid and precision (at
 // rlbm_init_fields, so that no step allocates).
@@ -631,18 +870,14 @@ int push_setup(rlbm_ctx c, std::string& err)
     push_free(c);
     std::vector<VelRec<double>> vd;
     build_vel_table(c->q, c->dt, vd);
-    const int nm = nmax_of(c->q.N);
-    if (c->prec == RLBM_F32) {
-        if (nm == 3) return upload_push_t<float, 3>(c, vd, c->prec, err);
-        if (nm == 5) return upload_push_t<float, 5>(c, vd, c->prec, err);
-        return upload_push_t<float, 7>(c, vd, c->prec, err);
+    switch (c->prec) {
+        case RLBM_F32: return push_setup_n<float, float, false>(c, vd, err);
+        case RLBM_F64: return push_setup_n<double, double, false>(c, vd, err);
+        case RLBM_BF16DEV: return push_setup_n<float, unsigned short, true>(c, vd, err);
+        case RLBM_F32DEV: return push_setup_n<float, float, true>(c, vd, err);
+        case RLBM_F64DEV: return push_setup_n<double, double, true>(c, vd, err);
     }
-    if (c->prec == RLBM_F64) {
-        if (nm == 3) return upload_push_t<double, 3>(c, vd, c->prec, err);
-        if (nm == 5) return upload_push_t<double, 5>(c, vd, c->prec, err);
-        return upload_push_t<double, 7>(c, vd, c->prec, err);
-    }
-    err = "the push kernel supports FP32 and FP64";
+    err = "unknown precision";
     return RLBM_EINVAL;
 }
 
@@ -656,6 +891,7 @@ PushParams make_push_params(rlbm_ctx c)
     P.paddr = static_cast<const PAddr*>(c->d_paddr);
     P.prec = c->d_prec;
     P.seg = static_cast<const PSeg*>(c->d_pseg);
+    P.ytab = c->d_pytab;
     P.G = c->d_G;
     P.Pc = c->d_Pc;
     P.nx = c->nx; P.ny = c->ny; P.Np = c->q.Np; P.bcx = c->bcx; P.bcy = c->bcy;
@@ -670,22 +906,35 @@ PushParams make_push_params(rlbm_ctx c)
 }
 }  // namespace
 
-hipError_t launch_push(rlbm_ctx c, bool init)
+namespace {
+template <typename T, typename ST, bool DEV>
+hipError_t launch_push_n(rlbm_ctx c, bool init, const PushParams& P)
 {
-    const PushParams P = make_push_params(c);
     const void* fin = c->f[c->cur];
     void* fout = c->f[c->cur ^ 1];
     const void* pin = c->pp[c->pcur];
     void* pout = init ? c->pp[c->pcur] : c->pp[c->pcur ^ 1];
-    const int nm = nmax_of(c->q.N);
-    if (c->prec == RLBM_F32) {
-        if (nm == 3) return launch_push_t<float, 3>(init, fin, fout, pin, pout, P, c->st);
-        if (nm == 5) return launch_push_t<float, 5>(init, fin, fout, pin, pout, P, c->st);
-        return launch_push_t<float, 7>(init, fin, fout, pin, pout, P, c->st);
+    const void* cin = DEV ? c->cf[c->cur] : nullptr;
+    void* cout = DEV ? c->cf[c->cur ^ 1] : nullptr;
+    switch (nmax_of(c->q.N)) {
+        case 3: return launch_push_t<T, ST, 3, DEV>(init, fin, fout, pin, pout, cin, cout, P, c->st);
+        case 5: return launch_push_t<T, ST, 5, DEV>(init, fin, fout, pin, pout, cin, cout, P, c->st);
+        default: return launch_push_t<T, ST, 7, DEV>(init, fin, fout, pin, pout, cin, cout, P, c->st);
     }
-    if (nm == 3) return launch_push_t<double, 3>(init, fin, fout, pin, pout, P, c->st);
-    if (nm == 5) return launch_push_t<double, 5>(init, fin, fout, pin, pout, P, c->st);
-    return launch_push_t<double, 7>(init, fin, fout, pin, pout, P, c->st);
+}
+}  // namespace
+
+hipError_t launch_push(rlbm_ctx c, bool init)
+{
+    const PushParams P = make_push_params(c);
+    switch (c->prec) {
+        case RLBM_F32: return launch_push_n<float, float, false>(c, init, P);
+        case RLBM_F64: return launch_push_n<double, double, false>(c, init, P);
+        case RLBM_BF16DEV: return launch_push_n<float, unsigned short, true>(c, init, P);
+        case RLBM_F32DEV: return launch_push_n<float, float, true>(c, init, P);
+        case RLBM_F64DEV: return launch_push_n<double, double, true>(c, init, P);
+    }
+    return hipErrorInvalidValue;
 }
 
 // Batched form.  push_prepare: tables and buffers of a push-kernel problem,

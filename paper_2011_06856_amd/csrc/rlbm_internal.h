@@ -439,9 +439,29 @@ struct rlbm_ctx_s {
     int pcur = 0;
     int pnrec = 0;                       // records in the push tables
     int pvalid = 0;                      // pp[pcur] holds the partial sums of f[cur]
+    // deviation storage (deviation.hip, push.hip): per-shell equilibrium
+    // coefficients paired with f[b] (in the workspace), the push kernel's
+    // per-segment monomial sums Y of the equilibrium basis, and the
+    // per-shell moment sums Z of the field output
+    void* cf[2] = {nullptr, nullptr};
+    void* d_pytab = nullptr;
+    double* d_dz = nullptr;
 };
 
 inline int nmax_of(int N) { return N <= 3 ? 3 : (N <= 5 ? 5 : 7); }
+
+// Deviation storage: g = f - F with the equilibrium F as coefficients.
+inline bool is_dev(int prec) { return prec == RLBM_BF16DEV || prec == RLBM_F32DEV || prec == RLBM_F64DEV; }
+inline bool valid_prec(int prec) { return prec >= RLBM_F64 && prec <= RLBM_F64DEV; }
+// Bytes of one stored population (or deviation).
+inline size_t store_size(int prec)
+{
+    return (prec == RLBM_F64 || prec == RLBM_F64DEV) ? 8 : (prec == RLBM_BF16DEV ? 2 : 4);
+}
+// Bytes of the arithmetic type (partial sums, equilibrium coefficients).
+inline size_t arith_size(int prec) { return (prec == RLBM_F64 || prec == RLBM_F64DEV) ? 8 : 4; }
+// Coefficient planes of the deviation storage: Np x (2 NMAX(N) + 1).
+inline int dev_planes(int Np, int N) { return Np * (2 * nmax_of(N) + 1); }
 SCParams make_params(rlbm_ctx c, int waves);   // capi.cpp
 
 // A WALL or FIXED axis: upwind points outside the grid need the tile
@@ -475,6 +495,13 @@ hipError_t launch_batch_step(int prec, int nmax, int waves, int grid, const Batc
 hipError_t launch_reset_counters(int* counters, hipStream_t st);
 hipError_t launch_batch_flat(int prec, int nmax, int waves, int items, const BatchDesc* descs, int nprob, int parity,
                              const double* Pc, int max_np, hipStream_t st);
+
+// Deviation storage (deviation.hip).
+int dev_setup(rlbm_ctx c, std::string& err);
+hipError_t launch_dev_init(rlbm_ctx c, hipStream_t st);
+hipError_t launch_dev_fields(rlbm_ctx c, double* out, double* partials, hipStream_t st);
+// Sum of per-block partial charges into 4 device doubles (kernels.hip).
+hipError_t launch_charges_sum(const double* partials, int nb, double* charges, hipStream_t st);
 
 // Push kernel (push.hip).
 void push_free(rlbm_ctx c);

@@ -14,10 +14,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.path.join(_HERE, "librlbm.so")
 
 RLBM_OK, RLBM_EINVAL, RLBM_ENOMEM, RLBM_EDEVICE, RLBM_ENONPHYS, RLBM_ESTATE = 0, -1, -2, -3, -4, -5
-RLBM_F64, RLBM_F32 = 0, 1
+RLBM_F64, RLBM_F32, RLBM_BF16DEV, RLBM_F32DEV, RLBM_F64DEV = 0, 1, 2, 3, 4
 RLBM_BC_PERIODIC, RLBM_BC_CLAMP = 0, 1
-PRECISIONS = {"f64": RLBM_F64, "f32": RLBM_F32}
-ELEM_BYTES = {RLBM_F64: 8, RLBM_F32: 4}
+PRECISIONS = {"f64": RLBM_F64, "f32": RLBM_F32, "bf16dev": RLBM_BF16DEV, "f32dev": RLBM_F32DEV,
+              "f64dev": RLBM_F64DEV}
+ELEM_BYTES = {RLBM_F64: 8, RLBM_F32: 4, RLBM_BF16DEV: 2, RLBM_F32DEV: 4, RLBM_F64DEV: 8}
+DEVIATION = (RLBM_BF16DEV, RLBM_F32DEV, RLBM_F64DEV)
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _vp = ctypes.c_void_p
@@ -270,6 +272,12 @@ class Solver:
         return b.value
 
     def get_populations(self):
+        """Plain storage: f as (nvel, ny, nx).  Deviation storage: the raw
+        checkpoint bytes (deviations, then equilibrium coefficients)."""
+        if self.precision in DEVIATION:
+            buf = np.empty(self.populations_bytes(), dtype=np.uint8)
+            self._check(lib().rlbm_get_populations(self._h, _vp(buf.ctypes.data), buf.nbytes))
+            return buf
         dt = {RLBM_F64: np.float64, RLBM_F32: np.float32}[self.precision]
         buf = np.empty(self.populations_bytes() // np.dtype(dt).itemsize, dtype=dt)
         self._check(lib().rlbm_get_populations(self._h, _vp(buf.ctypes.data), buf.nbytes))

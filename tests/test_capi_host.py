@@ -120,7 +120,11 @@ def test_invalid_arguments_are_rejected_without_a_device():
     # two buffers of 256 + 1 planes, four FP64 field planes, and the push
     # kernel's two partial-sum buffers (3 row slots x 8 moments per site)
     assert b.value >= (2 * 257 * 4 + 4 * 8 + 2 * 3 * 8 * 4) * 1024 * 1024
-    assert L.rlbm_workspace_bytes(h, 1024, 1024, 2, ctypes.byref(b)) == R.RLBM_EINVAL   # no such precision
+    assert L.rlbm_workspace_bytes(h, 1024, 1024, 5, ctypes.byref(b)) == R.RLBM_EINVAL   # no such precision
+    # bfloat16 deviations: two buffers of 256 + 1 planes of 2 bytes, and two
+    # buffers of 4 shells x 7 FP32 equilibrium coefficients per site
+    assert L.rlbm_workspace_bytes(h, 1024, 1024, R.RLBM_BF16DEV, ctypes.byref(b)) == R.RLBM_OK
+    assert b.value >= (2 * 257 * 2 + 2 * 4 * 7 * 4 + 4 * 8 + 2 * 3 * 8 * 4) * 1024 * 1024
     assert L.rlbm_set_waves(h, 17) == R.RLBM_EINVAL
     assert L.rlbm_destroy(h) == R.RLBM_OK
 
