@@ -193,37 +193,59 @@ def field_errors(a, ref):
 
 def precision_form(a):
     """Precision form: the quadrant Riemann problem at 2048^2 (periodic),
-    Np=6 x K=256 (1536 velocities), order 5, Kn=10.  FP32 populations timed;
-    the same steps in FP64 on the GPU give the per-field error of FP32."""
+    Np=6 x K=256 (1536 velocities), order 5, Kn=10, with FP32 populations and
+    with bfloat16 deviations from the local equilibrium (BF16DEV), both timed;
+    the same steps in FP64 on the GPU give their per-field errors at full
+    size.  (Their errors against the FP64 oracle, on a reduced grid of the
+    same problem after 1000 steps, are measured by
+    tests/test_gpu_deviation.py.)"""
     import torch
     side = a.side if a.side != 1024 else 2048
     cfg = W.quadrant_shock(side, steps=a.steps)
-    print("bench: precision form %s f32 steps=%d" % (cfg["name"], a.steps), file=sys.stderr, flush=True)
-    r32 = gpu_run(cfg, a.steps, a.warmup, "f32", a.waves, keep_fields=True)
-    torch.cuda.empty_cache()
-    print("bench: precision form f64 reference", file=sys.stderr, flush=True)
-    r64 = gpu_run(cfg, a.steps, a.warmup, "f64", 0, keep_fields=True)
-    torch.cuda.empty_cache()
-    launch_ms = r32["event_ms"] / a.steps
+    runs = {}
+    for prec in ("f32", "bf16dev", "f64"):
+        print("bench: precision form %s %s steps=%d" % (cfg["name"], prec, a.steps), file=sys.stderr, flush=True)
+        runs[prec] = gpu_run(cfg, a.steps, a.warmup, prec, a.waves if prec == "f32" else 0, keep_fields=True)
+        torch.cuda.empty_cache()
+    r32, rb, r64 = runs["f32"], runs["bf16dev"], runs["f64"]
     sv = r32["sv"]
-    achieved = BYTES_PER_SV["f32"] * sv / a.steps / (launch_ms * 1e-3) / 1e9
+    S = side * side
+    # algorithmic bytes per launch: FP32 one 4-byte read and write per
+    # site-velocity; BF16DEV 2 + 2 bytes plus the per-site equilibrium
+    # coefficients (6 shells x 11, FP32) read and written once
+    bytes32 = 8 * sv / a.steps
+    bytesb = 4 * sv / a.steps + 2 * 4 * 6 * 11 * S
+
+    def roof(r, nbytes, traffic_name):
+        launch_ms = r["event_ms"] / a.steps
+        ach = nbytes / (launch_ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "traffic": counter_traffic(traffic_name) if r["kernel"] == "push" else None,
+                "kernel": "k_push_step" if r["kernel"] == "push" else "k_stream_collide",
+                "algorithmic_bytes_per_sv": nbytes / (sv / a.steps), "avg_launch_ms": launch_ms}
+
+
+    def charges_vs64(r):
+        # global charges (sum N^0, T^00, T^0x, T^0y) minus FP64's, relative to the FP64 sums of N^0 and T^00
+        return [float((x - y) / abs(r64["charges"][0 if i == 0 else 1]))
+                for i, (x, y) in enumerate(zip(r["charges"], r64["charges"]))]
+
     return {
         "metric": METRIC, "value": sv / r32["wall_s"] / 1e9, "unit": "GSVUPS", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": 1e3 * r32["wall_s"] / a.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": cfg["name"] + "_order5", "grid": [side, side], "velocities": 1536, "order": 5,
-                   "kernel": r32["kernel"], "fields_finite": r32["finite"] and r64["finite"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": counter_traffic("push_step_f32_quadrant_%d" % side) if r32["kernel"] == "push" else None,
-                     "kernel": "k_push_step" if r32["kernel"] == "push" else "k_stream_collide",
-                     "algorithmic_bytes_per_sv": 8, "avg_launch_ms": launch_ms},
+                   "kernel": r32["kernel"], "fields_finite": r32["finite"] and rb["finite"] and r64["finite"]},
+        "roofline": roof(r32, bytes32, "push_step_f32_quadrant_%d" % side),
+        "fp32_error_vs_fp64": field_errors(r32["fields"], r64["fields"]),
+        "charges_fp32_minus_fp64": charges_vs64(r32),
+        "bf16dev": {"value": sv / rb["wall_s"] / 1e9, "unit": "GSVUPS", "ms_per_step": 1e3 * rb["wall_s"] / a.steps,
+                    "dtype": "bf16 deviations, f32 arithmetic",
+                    "roofline": roof(rb, bytesb, "push_step_bf16dev_quadrant_%d" % side),
+                    "error_vs_fp64": field_errors(rb["fields"], r64["fields"]),
+                    "charges_minus_fp64": charges_vs64(rb)},
         "fp64_reference": {"gsvups_events": sv / (r64["event_ms"] * 1e-3) / 1e9,
                            "avg_launch_ms": r64["event_ms"] / a.steps},
-        "fp32_error_vs_fp64": field_errors(r32["fields"], r64["fields"]),
-        # global charges (sum N^0, T^00, T^0x, T^0y): FP32 minus FP64, relative to the FP64 sums of N^0 and T^00
-        "charges_fp32_minus_fp64": [float((x - y) / abs(r64["charges"][0 if i == 0 else 1]))
-                                    for i, (x, y) in enumerate(zip(r32["charges"], r64["charges"]))],
     }
 
 

@@ -114,9 +114,10 @@ __device__ __forceinline__ unsigned short to_st<unsigned short, float>(float v, 
 {
     // v_cvt_sr_bf16_f32 adds the high 16 bits of r to the 16 discarded bits
     // and truncates; the result is a bfloat16 pair (low half written here)
+    // (the untouched high half is v's own: no extra register is cleared)
     typedef __bf16 b2 __attribute__((ext_vector_type(2)));
-    const b2 z = {};
-    return __builtin_bit_cast(unsigned short, __builtin_amdgcn_cvt_sr_bf16_f32(z, v, r, false)[0]);
+    return __builtin_bit_cast(unsigned short,
+                              __builtin_amdgcn_cvt_sr_bf16_f32(__builtin_bit_cast(b2, v), v, r, false)[0]);
 }
 
 // 32-bit finaliser of MurmurHash3 (Appleby): a bijective mix of the bits.
@@ -141,7 +142,7 @@ struct PushParams {
     const PAddr* paddr;      // PAddr[]
     const void* prec;        // PRec<T, NH>[]
     const PSeg* seg;         // [4][Np]
-    const void* ytab;        // deviation storage: [4][Np][2 NM + 1][9] (T), Y[q][i][t][j] = sum over the
+    const void* ytab;        // deviation storage: [4][Np][push_ys(NM)] (T), Y[q][i][t * 9 + j] = sum over the
                              // segment's velocities of H_t mono_j, mono = (1, c, s, c^2, c s, c^3, c^2 s,
                              // c^3 s, c^2 s^2); null otherwise
     const double* G;
@@ -269,17 +270,31 @@ __device__ __forceinline__ void corner_series(AT al, AT be, LoadC loadc, AT* De)
     }
 }
 
+// LDS entries per wave (arithmetic type): the halo accumulator, the row
+// slots and, for deviation storage, the site's equilibrium coefficients of
+// the current shell ([2 NM + 1][64]).
+__host__ __device__ constexpr int push_acc_entries() { return 96 + 3 * NMOM * 64; }
+__host__ __device__ constexpr int push_wlds(int NM, bool dev) { return push_acc_entries() + (dev ? (2 * NM + 1) * 64 : 0); }
+
+// Entries per segment of the deviation form's Y table as staged in LDS (the
+// 9 x (2 NM + 1) sums, padded to whole 16-byte rows).
+__host__ __device__ constexpr int push_ys(int NM) { return ((2 * NM + 1) * 9 + 3) / 4 * 4; }
+
 // One wave-tile: 64 sites of row ty starting at column 64 tx.  INIT computes
 // only the partial sums of the current populations (no stream, no
 // collision, no population store).  lh: this wave's LDS, the 96-entry halo
-// accumulator [edge][dir][d][k] followed by the row slots [d][k][64].
+// accumulator [edge][dir][d][k] followed by the row slots [d][k][64] and,
+// for deviation storage, the coefficients [2 NM + 1][64].
+// ylds (DEV): the work-group's copy of the Y table, push_ys(NM) entries per
+// segment.
 // T is the arithmetic type, ST the storage type of the populations (plain)
 // or of the deviations (DEV, with the per-shell equilibrium coefficients in
 // cin / cout, [Np][2 NM + 1][S] of T).
 template <typename T, typename ST, int NM, int LB, bool INIT, bool DEV>
 __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __restrict__ fout, const T* __restrict__ pin,
                                           T* __restrict__ pout, const T* __restrict__ cin, T* __restrict__ cout,
-                                          const PushParams& P, int tile, T* __restrict__ lh, bool live)
+                                          const PushParams& P, int tile, T* __restrict__ lh, const T* ylds,
+                                          bool live)
 {
     constexpr int NT = 2 * NM + 1;
     constexpr int NH = push_nh(NM, DEV);
@@ -294,7 +309,6 @@ __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __rest
     CSeg* const seg = (CSeg*)P.seg;
     CDbl* const Gtab = (CDbl*)P.G;
     CDbl* const Pc = (CDbl*)P.Pc;
-    CTab* const ytab = (CTab*)P.ytab;
 
     const int lane = threadIdx.x & 63;
     const int ntx = (P.nx + 63) >> 6;
@@ -390,6 +404,7 @@ __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __rest
     // row slots d = 0, 1, 2 (dy 0, +1, -1), touched once per segment: in
     // this wave's LDS after the halo accumulator, lane-contiguous
     T* const lrow = lh + 96;
+    T* const lcc = lh + push_acc_entries();   // DEV: [2 NM + 1][64]
     auto R = [&](int d, int k) __attribute__((always_inline)) -> T& { return lrow[(d * NMOM + k) * 64 + lane]; };
 #pragma unroll
     for (int d = 0; d < 3; ++d)
@@ -426,6 +441,12 @@ __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __rest
 #pragma unroll
                 for (int t = 0; t < NT; ++t) cc[t] = cin[(long long)(i * NT + t) * S + site];
             }
+            // DEV: the coefficients go to this wave's LDS, read back per
+            // segment (few registers stay live across the quadrants)
+            if (DEV) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) lcc[t * 64 + lane] = cc[t];
+            }
 #pragma unroll 1
             for (int q = 0; q < 4; ++q) {
                 const int sx = qsx(q), sy = qsy(q);
@@ -446,13 +467,20 @@ __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __rest
                                          },
                                          D);
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) D[t] -= cc[t];
+                    for (int t = 0; t < NT; ++t) D[t] -= lcc[t * 64 + lane];
                 }
-                T Sm[9];   // sum f, f c, f s, f c^2, f c s, f c^3, f c^2 s, f c^3 s, f c^2 s^2
+                // sum f, f c, f s, f c^2, f c s, f c^3, f c^2 s, f c^3 s,
+                // f c^2 s^2 over the segment: each load batch's sums start from
+                // zero in T and are carried into FP64 (compensated: T rounds
+                // only within a batch)
+                double Sm[9];
 #pragma unroll
-                for (int j = 0; j < 9; ++j) Sm[j] = T(0);
+                for (int j = 0; j < 9; ++j) Sm[j] = 0.0;
                 const int v0 = G.begin;
                 for (int kb = 0; kb < G.nbatch; ++kb) {
+                    T Sb[9];
+#pragma unroll
+                    for (int j = 0; j < 9; ++j) Sb[j] = T(0);
                     // the records RLBM_PUSH_PREFETCH batches on (the table runs
                     // on across segments): one word of each scalar-cache line,
                     // taken in only at the end of this batch
@@ -523,23 +551,24 @@ __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __rest
                         }
                         // explicit FMAs: the step and the rebuild (INIT) must
                         // produce the same partial sums bit for bit
-                        Sm[0] += fnew;
+                        Sb[0] += fnew;
 #pragma unroll
-                        for (int j = 0; j < 8; ++j) Sm[1 + j] = fma(fnew, (T)Rr.mono[j], Sm[1 + j]);
+                        for (int j = 0; j < 8; ++j) Sb[1 + j] = fma(fnew, (T)Rr.mono[j], Sb[1 + j]);
                     }
+#pragma unroll
+                    for (int j = 0; j < 9; ++j) Sm[j] += (double)Sb[j];
                     if (RLBM_PUSH_PREFETCH > 0) asm volatile("" ::"s"(pf));
                 }
                 // DEV: add the monomial sums of the equilibrium part F of the
                 // stored state, sum_t C_t Y_t (explicit FMAs, same order in
                 // the step and the rebuild)
                 if (DEV) {
-                    CTab* yq = ytab + (size_t)(q * P.Np + i) * NT * 9;
+                    const T* yq = ylds + (q * P.Np + i) * push_ys(NM);
+#pragma unroll 1
+                    for (int t = 0; t < NT; ++t) {
+                        const double c = (double)lcc[t * 64 + lane];
 #pragma unroll
-                    for (int j = 0; j < 9; ++j) {
-                        T acc = Sm[j];
-#pragma unroll
-                        for (int t = 0; t < NT; ++t) acc = fma(cc[t], (T)yq[t * 9 + j], acc);
-                        Sm[j] = acc;
+                        for (int j = 0; j < 9; ++j) Sm[j] = fma(c, (double)yq[t * 9 + j], Sm[j]);
                     }
                 }
                 // fold the monomial sums into the weighted moment sums of the
@@ -550,28 +579,33 @@ __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __rest
                 // contraction here, so that both instantiations round alike.
                 {
 #pragma clang fp contract(off)
-                const T al = dt * (T)sx, be = dt * (T)sy, ga = al * be;
-                const T S1 = Sm[0], Sc = Sm[1], Ss = Sm[2], Scc = Sm[3], Scs = Sm[4], Sccc = Sm[5], Sccs = Sm[6],
-                        Scccs = Sm[7], Sccss = Sm[8];
-                const T Sss = S1 - Scc, Scss = Sc - Sccc;
+                // The fold runs in FP64 with the step's bilinear weights (dt in
+                // T, as the tables hold it); each segment's corner parts are
+                // rounded once to T as they enter the row slots.
+                const double al = (double)(dt * (T)sx), be = (double)(dt * (T)sy), ga = al * be;
+                const double S1 = Sm[0], Sc = Sm[1], Ss = Sm[2], Scc = Sm[3], Scs = Sm[4], Sccc = Sm[5],
+                             Sccs = Sm[6], Scccs = Sm[7], Sccss = Sm[8];
+                const double Sss = S1 - Scc, Scss = Sc - Sccc;
                 // (T, Tc, Ts, Tcs) of e = 1, c, s, c^2, c s
-                const T Te[5][4] = {{S1, Sc, Ss, Scs},
-                                    {Sc, Scc, Scs, Sccs},
-                                    {Ss, Scs, Sss, Scss},
-                                    {Scc, Sccc, Sccs, Scccs},
-                                    {Scs, Sccs, Scss, Sccss}};
-                const T p = (T)G.p, p2 = (T)(G.p * G.p);
+                const double Te[5][4] = {{S1, Sc, Ss, Scs},
+                                         {Sc, Scc, Scs, Sccs},
+                                         {Ss, Scs, Sss, Scss},
+                                         {Scc, Sccc, Sccs, Scccs},
+                                         {Scs, Sccs, Scss, Sccss}};
+                const double p = G.p, p2 = G.p * G.p;
+                const double actd = (double)act;
                 // moment k: angular factor e(k), radial factor p or p^2
                 constexpr int EK[NMOM] = {0, 1, 2, 0, 1, 2, 3, 4};
                 const int dir = sx > 0 ? 0 : 1;
 #pragma unroll
                 for (int k = 0; k < NMOM; ++k) {
-                    const T* t4 = Te[EK[k]];
-                    const T r = k < 3 ? p : p2;
-                    const T c3 = act * r * (ga * t4[3]);
-                    const T c1 = act * r * (al * t4[1]) - c3;
-                    const T c2 = act * r * (be * t4[2]) - c3;
-                    const T c0 = act * r * t4[0] - c1 - c2 - c3;
+                    const double* t4 = Te[EK[k]];
+                    const double r = k < 3 ? p : p2;
+                    const double d3 = actd * r * (ga * t4[3]);
+                    const double d1 = actd * r * (al * t4[1]) - d3;
+                    const double d2 = actd * r * (be * t4[2]) - d3;
+                    const T c0 = (T)(actd * r * t4[0] - d1 - d2 - d3);
+                    const T c1 = (T)d1, c2 = (T)d2, c3 = (T)d3;
                     // x-displaced parts move to their target column inside the
                     // wave; the tile's edge columns also keep them for the halo
                     R(0, k) += c0 + from_upwind(c1, sx);
@@ -637,11 +671,20 @@ __global__ __launch_bounds__(256, RLBM_PUSH_WPE) void k_push_step(const ST* __re
     int band, col;
     push_wg_tile(b, ntx, P.ny, P.sb, band, col);
     const int ty = band * 4 + wv;
-    if (ty >= P.ny) return;   // whole waves; the kernel has no barrier
+    T* const ylds = reinterpret_cast<T*>(psmem) + 4 * push_wlds(NM, DEV);
+    if (DEV) {
+        // the work-group's copy of the Y table (read with broadcast LDS loads
+        // in each segment's fold); the kernel's only barrier
+        using CTab = const PUSH_CONST_AS T;
+        const int n = 4 * P.Np * push_ys(NM);
+        for (int j = threadIdx.x; j < n; j += 256) ylds[j] = ((CTab*)P.ytab)[j];
+        __syncthreads();
+    }
+    if (ty >= P.ny) return;   // whole waves
     const bool live = true;
     const int tile = ty * ntx + col;
-    T* lh = reinterpret_cast<T*>(psmem) + (size_t)wv * (96 + 3 * NMOM * 64);
-    push_tile<T, ST, NM, LB, INIT, DEV>(fin, fout, pin, pout, cin, cout, P, tile, lh, live);
+    T* lh = reinterpret_cast<T*>(psmem) + (size_t)wv * push_wlds(NM, DEV);
+    push_tile<T, ST, NM, LB, INIT, DEV>(fin, fout, pin, pout, cin, cout, P, tile, lh, ylds, live);
 }
 
 // Batched form: the push-kernel problems of a batch advance together in one
@@ -676,10 +719,10 @@ __global__ __launch_bounds__(256, RLBM_PUSH_WPE) void k_push_batch(const PushDes
     const int ty = band * 4 + wv;
     if (ty >= P.ny) return;   // whole waves; the kernel has no barrier
     const int tile = ty * ntx + col;
-    T* lh = reinterpret_cast<T*>(psmem) + (size_t)wv * (96 + 3 * NMOM * 64);
+    T* lh = reinterpret_cast<T*>(psmem) + (size_t)wv * push_wlds(NM, false);
     push_tile<T, T, NM, LB, false, false>(static_cast<const T*>(D.f[parity]), static_cast<T*>(D.f[parity ^ 1]),
                                           static_cast<const T*>(D.pp[parity]), static_cast<T*>(D.pp[parity ^ 1]),
-                                          nullptr, nullptr, P, tile, lh, true);
+                                          nullptr, nullptr, P, tile, lh, nullptr, true);
 }
 
 // Load batch per precision: FP64 holds half as many values per register.
@@ -694,7 +737,19 @@ hipError_t launch_push_t(bool init, const void* fin, void* fout, const void* pin
 {
     constexpr int LB = PushLB<T>::value;
     const unsigned blocks = (unsigned)(((P.nx + 63) / 64) * ((P.ny + 3) / 4));
-    const size_t lds = (size_t)4 * (96 + 3 * NMOM * 64) * sizeof(T);   // 4 waves x (halo + row slots)
+    // 4 waves x (halo + row slots), and the Y table of the deviation form
+    const size_t lds = ((size_t)4 * push_wlds(NM, DEV) + (DEV ? (size_t)4 * P.Np * push_ys(NM) : 0)) * sizeof(T);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    if (lds > 64 * 1024) {   // beyond the default limit of dynamic LDS: opt in (set once per size)
+        static size_t configured[2] = {0, 0};
+        if (lds > configured[init]) {
+            const void* fn = init ? reinterpret_cast<const void*>(&k_push_step<T, ST, NM, LB, true, DEV>)
+                                  : reinterpret_cast<const void*>(&k_push_step<T, ST, NM, LB, false, DEV>);
+            const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            configured[init] = lds;
+        }
+    }
     if (init)
         hipLaunchKernelGGL((k_push_step<T, ST, NM, LB, true, DEV>), dim3(blocks), dim3(256), lds, st,
                            (const ST*)fin, (ST*)fout, (const T*)pin, (T*)pout, (const T*)cin, (T*)cout, P);
@@ -708,7 +763,7 @@ template <typename T, int NM>
 hipError_t launch_push_batch_t(const void* descs, int nprob, int wgs, int parity, hipStream_t st)
 {
     constexpr int LB = PushLB<T>::value;
-    const size_t lds = (size_t)4 * (96 + 3 * NMOM * 64) * sizeof(T);
+    const size_t lds = (size_t)4 * push_wlds(NM, false) * sizeof(T);
     hipLaunchKernelGGL((k_push_batch<T, NM, LB>), dim3((unsigned)wgs), dim3(256), lds, st,
                        static_cast<const PushDesc*>(descs), nprob, parity);
     return hipGetLastError();
@@ -729,7 +784,7 @@ int upload_push_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, std::string
     std::vector<PAddr> adrs;
     std::vector<PSeg> segs(4 * (size_t)Np);
     std::vector<T> ytab;
-    if (DEV) ytab.assign((size_t)4 * Np * NT * 9, T(0));
+    if (DEV) ytab.assign((size_t)4 * Np * push_ys(NM), T(0));
     // padding records: zero weights and equilibrium row, a store to the
     // spare plane, loads from the plane of the record before them (cache
     // hits, no extra HBM reads)
@@ -779,7 +834,7 @@ int upload_push_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, std::string
             }
             if (DEV)
                 for (int t = 0; t < NT; ++t)
-                    for (int k = 0; k < 9; ++k) ytab[((size_t)(q * Np + i) * NT + t) * 9 + k] = (T)Y[t][k];
+                    for (int k = 0; k < 9; ++k) ytab[(size_t)(q * Np + i) * push_ys(NM) + t * 9 + k] = (T)Y[t][k];
             while (count % LB) {
                 PAddr nulla;
                 std::memset(&nulla, 0, sizeof(nulla));

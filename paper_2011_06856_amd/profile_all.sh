@@ -1,7 +1,8 @@
 #!/bin/bash
 # rocprofv3 summaries of the two step kernels on their benchmark workloads:
 #   k_stream_collide  circular shock 1024^2, 256 velocities, FP32 (tile kernel)
-#   k_push_step       quadrant problem 2048^2, 1536 velocities, order 5, FP32 (push kernel)
+#   k_push_step       quadrant problem 2048^2, 1536 velocities, order 5, FP32 and
+#                     bfloat16 deviations (push kernel)
 # Per workload: a kernel-trace/stats run, then a FETCH_SIZE run and a WRITE_SIZE
 # run (counters in passes of their own), each ending with a 1 GiB device copy
 # that calibrates the counters to bytes.  Run from the repository root on a
@@ -34,8 +35,13 @@ run() {   # name, kernel, launch bytes, wave-velocities per launch, stats args, 
 # wave-velocities: site-velocity updates / 64
 run stream_collide_f32_circular_1024 "k_stream_collide<float, float, 3, 64, false>" 2147483648 4194304 \
     "--steps 200" "--steps 4"
-run push_step_f32_quadrant_2048 "k_push_step<float, 5, 8, false>" 51539607552 100663296 \
+run push_step_f32_quadrant_2048 "k_push_step<float, float, 5, 8, false, false>" 51539607552 100663296 \
     "--workload quadrant --side 2048 --steps 20" "--workload quadrant --side 2048 --steps 3"
+# bfloat16 deviations: 4 B per site-velocity plus the per-site equilibrium
+# coefficients (6 shells x 11 FP32, read and written: 528 B per site)
+run push_step_bf16dev_quadrant_2048 "k_push_step<float, unsigned short, 5, 8, false, true>" 27980857344 100663296 \
+    "--workload quadrant --side 2048 --steps 20 --precision bf16dev" \
+    "--workload quadrant --side 2048 --steps 3 --precision bf16dev"
 
 # The 48-problem batch (FP32, the library's default work-group shape and
 # mode, one graph replay per step): kernel statistics only, with the kernel
