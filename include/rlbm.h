@@ -106,7 +106,9 @@ int rlbm_get_quadrature(rlbm_ctx ctx, double* p, double* theta, double* w);
  * the given precision: two population buffers of nvel + 1 planes, the field
  * outputs (4 doubles per site), the partial charges, and the two partial-sum
  * buffers of the push kernel (3 row slots x 8 moments per site plus a halo
- * per tile edge), present whichever step kernel is used. */
+ * per tile edge), present whichever step kernel is used, and for deviation
+ * storage two buffers of equilibrium coefficients (Np x (2 Nm + 1) per site,
+ * FP32, or FP64 for RLBM_F64DEV). */
 int rlbm_workspace_bytes(rlbm_ctx ctx, int nx, int ny, int precision, size_t* bytes);
 
 /*
@@ -123,7 +125,11 @@ int rlbm_workspace_bytes(rlbm_ctx ctx, int nx, int ny, int precision, size_t* by
  *                 must stay in [0, 1]).
  *   bc_x, bc_y    RLBM_BC_PERIODIC, RLBM_BC_CLAMP, RLBM_BC_WALL (n_angle
  *                 even) or RLBM_BC_FIXED, per axis (see the enum above).
- *   precision     RLBM_F64 or RLBM_F32 population storage.
+ *   precision     population storage: RLBM_F64, RLBM_F32, or a deviation
+ *                 storage (RLBM_BF16DEV, RLBM_F32DEV, RLBM_F64DEV), which
+ *                 starts from g = 0 (f is exactly the truncated equilibrium
+ *                 of the fields) and needs periodic or clamped axes and
+ *                 Maxwell-Juttner statistics (RLBM_EINVAL otherwise).
  *   d_workspace   device memory of at least rlbm_workspace_bytes() bytes,
  *                 256-byte aligned, owned by the caller (e.g. a torch tensor)
  *                 and alive until rlbm_destroy; NULL lets the library
@@ -193,8 +199,14 @@ int rlbm_moments_device(rlbm_ctx ctx, double* d_fields, double* d_charges);
 
 /* Checkpoint: copy the current populations (storage precision, layout
  * f[v][y][x]) to / from a caller-owned host buffer of exactly
- * nvel * nx * ny * element-size bytes (8 for F64, 4 for F32); other sizes
- * give RLBM_EINVAL.  Synchronous. */
+ * rlbm_populations_bytes() bytes; other sizes give RLBM_EINVAL.  Plain
+ * storage: nvel * nx * ny elements (8 bytes for F64, 4 for F32).  Deviation
+ * storage: the deviations g[v][y][x] (2, 4 or 8 bytes for BF16DEV, F32DEV,
+ * F64DEV), then the equilibrium coefficients C[i][t][y][x] (FP32, FP32,
+ * FP64) of shell i and harmonic t = {1, cos th, sin th, ..., cos Nm th,
+ * sin Nm th} (2 Nm + 1 per shell), with f_v = g_v + w_v sum_t C[shell(v)][t]
+ * harmonic_t(th_v).  A run resumed from a checkpoint continues bit for bit.
+ * Synchronous. */
 int rlbm_populations_bytes(rlbm_ctx ctx, size_t* bytes);
 int rlbm_get_populations(rlbm_ctx ctx, void* host, size_t bytes);
 int rlbm_set_populations(rlbm_ctx ctx, const void* host, size_t bytes);
