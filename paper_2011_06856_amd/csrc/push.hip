@@ -563,13 +563,19 @@ __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __rest
                 // stored state, sum_t C_t Y_t (explicit FMAs, same order in
                 // the step and the rebuild)
                 if (DEV) {
+                    // (2 NM + 1 terms in T, carried into the FP64 sums once)
                     const T* yq = ylds + (q * P.Np + i) * push_ys(NM);
+                    T Sf[9];
+#pragma unroll
+                    for (int j = 0; j < 9; ++j) Sf[j] = T(0);
 #pragma unroll 1
                     for (int t = 0; t < NT; ++t) {
-                        const double c = (double)lcc[t * 64 + lane];
+                        const T c = lcc[t * 64 + lane];
 #pragma unroll
-                        for (int j = 0; j < 9; ++j) Sm[j] = fma(c, (double)yq[t * 9 + j], Sm[j]);
+                        for (int j = 0; j < 9; ++j) Sf[j] = fma(c, yq[t * 9 + j], Sf[j]);
                     }
+#pragma unroll
+                    for (int j = 0; j < 9; ++j) Sm[j] += (double)Sf[j];
                 }
                 // fold the monomial sums into the weighted moment sums of the
                 // segment's four corners: with T_e = sum f e, the corner sums
