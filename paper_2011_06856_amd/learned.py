@@ -16,9 +16,12 @@ HIP kernels; numpy only samples and normalises training rows on the host):
 2. training: mini-batch Adam on the GPU (rlbm_mlp_grad, rlbm_mlp_adam_step).
 3. use: after every coarse step, rlbm_mlp_correct adds the predicted change
    of the stress to the populations (conserving N^mu and T^0mu).
-4. reference: the plain fine-angle solver; errors are Eq. rel_err per field; the
-   equal-error angle count K* of the plain solver, by log-log interpolation
-   over a sweep of K, gives the speedup wall(plain K*) / wall(coarse + MLP).
+4. reference and fallback: the plain fine-angle solver; errors are Eq. rel_err
+   per field; the equal-error angle count K* of the plain solver, by log-log
+   interpolation over a sweep of K, gives the speedup wall(plain K*) /
+   wall(coarse + MLP).  In use (`corrected_fields`) a correction that is not
+   finite, not physical, or made on inputs outside the training range falls
+   back to the fine solver.
 """
 import os
 import sys
@@ -145,6 +148,11 @@ class Normaliser:
         self.in_sig = centre.std(axis=0) + 1e-6
         self.out_mu = T.mean(axis=0)
         self.out_sig = T.std(axis=0) + 1e-9
+        # the training inputs' range per normalised field (the trust region
+        # of the correction in use)
+        Xn = ((X[:, :63].reshape(-1, 9, 7) - self.in_mu) / self.in_sig).reshape(-1, 7)
+        self.in_lo = Xn.min(axis=0)
+        self.in_hi = Xn.max(axis=0)
 
     def inputs(self, X):
         """Normalised patches; column 63 carried over from X when it has one
@@ -244,6 +252,38 @@ def evaluate_readout(net, side, seeds, K_coarse, K_fine, steps):
         del c
         res.append(dict(seed=sd, Kn=Kn, plain=plain, corrected=corr, t_corrected=tc))
     return res
+
+
+def corrected_fields(net, norm, side, fld, tau, dt, Kn, steps, K_coarse=24, K_fine=384, margin=0.25):
+    """The learned form in use, with the plain fine-angle solver as its
+    fallback: a coarse run of `steps` steps and its readout correction are
+    returned unless the correction cannot be trusted, in which case the fine
+    run is made and its fields returned.  The correction is not trusted when
+    a corrected field is not finite or not physical (n <= 0, eps <= 0, |U|
+    not finite), or when the coarse run's normalised inputs leave the
+    training range by more than `margin` of its width (norm.in_lo / in_hi,
+    per field).  Returns (fields, source, reason) with source "network" or
+    "fine"."""
+    c = make_solver(K_coarse, side, fld, tau, dt)
+    c.step(steps)
+    net.set_extra(float(np.log10(Kn)))
+    X = net.features(c)[:, :63].cpu().numpy().reshape(-1, 7)
+    width = norm.in_hi - norm.in_lo
+    outside = bool((X < norm.in_lo - margin * width).any() or (X > norm.in_hi + margin * width).any())
+    n, eps, ux, uy = net.readout(c, float(np.log10(Kn)))
+    del c
+    reason = None
+    if not all(np.isfinite(a).all() for a in (n, eps, ux, uy)):
+        reason = "non-finite corrected field"
+    elif (n <= 0).any() or (eps <= 0).any():
+        reason = "non-physical corrected field"
+    elif outside:
+        reason = "inputs outside the training range"
+    if reason is None:
+        return dict(n=n, eps=eps, ux=ux, uy=uy), "network", None
+    f = make_solver(K_fine, side, fld, tau, dt)
+    f.step(steps)
+    return run_fields(f), "fine", reason
 
 
 def sweep_plain(side, seeds, Ks, K_fine, steps):

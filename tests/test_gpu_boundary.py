@@ -71,20 +71,22 @@ def test_reinit_after_rejected_arguments_keeps_the_context():
     check_fields(a.moments()[:4], ref.fields(), 1e-4, "reinit_other_grid")
 
 
-@pytest.mark.parametrize("kernel", ["tile", "push"])
-def test_step_captured_in_a_graph_replays_like_eager_steps(kernel):
+@pytest.mark.parametrize("kernel,prec", [("tile", "f32"), ("push", "f32"), ("push", "bf16dev")])
+def test_step_captured_in_a_graph_replays_like_eager_steps(kernel, prec):
     """rlbm_step(2) captured on the context's stream (torch's global capture
     mode rejects any allocation or synchronisation inside), replayed several
     times with eager work and synchronisations in between: every replay
-    leaves the populations of the same steps issued eagerly, bit for bit."""
+    leaves the populations of the same steps issued eagerly, bit for bit
+    (for bfloat16 deviations too: their stochastic rounding draws its random
+    stream from the stored state)."""
     import torch
     rl = _rlbm()
     nx, ny = 130, 20
     fld = W.quadrant(nx, ny, seed=4)
     st = torch.cuda.Stream()
-    g_run = rl.Solver(4, 48, 3).init_fields(nx, ny, *fld, tau=5.0, precision="f32", stream=st)
+    g_run = rl.Solver(4, 48, 3).init_fields(nx, ny, *fld, tau=5.0, precision=prec, stream=st)
     g_run.set_kernel(kernel)
-    ref = rl.Solver(4, 48, 3).init_fields(nx, ny, *fld, tau=5.0, precision="f32")
+    ref = rl.Solver(4, 48, 3).init_fields(nx, ny, *fld, tau=5.0, precision=prec)
     ref.set_kernel(kernel)
     g_run.step(1)      # the push kernel's partial sums are built by an eager step
     ref.step(1)
@@ -99,5 +101,5 @@ def test_step_captured_in_a_graph_replays_like_eager_steps(kernel):
         x = torch.randn(1 << 16, device="cuda")          # eager work between replays
         torch.cuda.synchronize()
         assert float(x.abs().sum()) > 0
-        say("graph %s replay %d" % (kernel, r))
-        assert np.array_equal(g_run.get_populations(), ref.get_populations()), (kernel, r)
+        say("graph %s %s replay %d" % (kernel, prec, r))
+        assert np.array_equal(g_run.get_populations(), ref.get_populations()), (kernel, prec, r)

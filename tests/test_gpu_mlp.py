@@ -339,3 +339,55 @@ def test_trained_readout_gains_on_held_out_seeds():
     assert losses[-1] < 0.9 * losses[0]
     for k in ("n", "eps", "beta"):
         assert corr[k] < 0.95 * plain[k], (k, corr[k], plain[k])
+    # in use, held-out runs stay inside the trust region: no fallback
+    for sd in (10000, 10001):
+        Kn, fld, tau, dt = Lr.shock(side, sd)
+        _, source, reason = Lr.corrected_fields(net, nm, side, fld, tau, dt, Kn, steps, Kc, Kf)
+        say("held-out seed %d: %s %s" % (sd, source, reason))
+        assert source == "network", (sd, reason)
+
+
+def test_fallback_to_the_fine_solver():
+    """The learned form in use falls back to the plain fine-angle solver when
+    the correction cannot be trusted: with a network whose weights hold a
+    NaN the corrected fields are not finite, and with a training range that
+    the run's inputs leave they are out of distribution; both times the
+    returned fields are those of the plain fine run, bit for bit.  With
+    sound weights and a range around the run's inputs the corrected fields
+    are used."""
+    rl = _rl()
+    from paper_2011_06856_amd import learned as Lr
+    side, Kc, Kf, steps = 64, 12, 48, 20
+    X, T = Lr.collect_readout(side, range(3), Kc, Kf, steps, rows=2048)
+    nm = Lr.Normaliser(X, T)
+    net = rl.MLP(max_batch=side * side, out_dim=4)
+    net.init_params(seed=3)
+    nm.apply(net)
+    Kn, fld, tau, dt = Lr.shock(side, 1)
+    fine = Lr.make_solver(Kf, side, fld, tau, dt)
+    fine.step(steps)
+    ref = Lr.run_fields(fine)
+    # sound weights and a training range well around the run's inputs (seed 1
+    # is a training seed; the range is widened so that sites outside the
+    # sampled rows stay inside it)
+    nm.in_lo, nm.in_hi = nm.in_lo - 10.0, nm.in_hi + 10.0
+    got, source, reason = Lr.corrected_fields(net, nm, side, fld, tau, dt, Kn, steps, Kc, Kf)
+    assert source == "network" and reason is None
+    assert all(np.isfinite(got[k]).all() for k in ("n", "eps", "ux", "uy"))
+    # a NaN weight: not finite
+    p = net.get_params()
+    p[0] = np.nan
+    net.set_params(p)
+    got, source, reason = Lr.corrected_fields(net, nm, side, fld, tau, dt, Kn, steps, Kc, Kf)
+    say("poisoned network: %s (%s)" % (source, reason))
+    assert source == "fine" and reason == "non-finite corrected field"
+    for k in ("n", "eps", "ux", "uy"):
+        assert np.array_equal(got[k], ref[k]), k
+    # sound weights again, a training range the inputs leave
+    net.init_params(seed=3)
+    nm.in_lo, nm.in_hi = nm.in_lo * 0.0, nm.in_lo * 0.0 + 1e-3
+    got, source, reason = Lr.corrected_fields(net, nm, side, fld, tau, dt, Kn, steps, Kc, Kf)
+    say("out-of-range inputs: %s (%s)" % (source, reason))
+    assert source == "fine" and reason == "inputs outside the training range"
+    for k in ("n", "eps", "ux", "uy"):
+        assert np.array_equal(got[k], ref[k]), k
