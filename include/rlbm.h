@@ -277,12 +277,14 @@ int rlbm_batch_count(rlbm_batch b);
 int rlbm_batch_problem(rlbm_batch b, int i, rlbm_ctx* ctx);
 
 /*
- * Advance every problem nsteps steps.  Each step is one persistent launch
- * whose work-groups take (problem, tile) items from per-XCD work queues until
- * all are drained; pairs of steps are replayed from a captured HIP graph
- * (the queue counters are cleared by a kernel node).  Asynchronous; allocates
- * nothing after the first call for a shape.  rlbm_batch_step_eager issues the
- * same launches without the graph.
+ * Advance every problem nsteps steps.  A step of the problems that the tile
+ * kernel serves is one persistent launch whose work-groups take (problem,
+ * tile) items from per-XCD work queues until all are drained (the launch
+ * leaves its queue counters at zero for the next one); the problems that the
+ * push kernel serves (RLBM_KERNEL_AUTO's choice, as for one problem) follow
+ * in one flat launch.  Pairs of steps are replayed from a captured HIP graph.
+ * Asynchronous; allocates nothing after the first call for a shape.
+ * rlbm_batch_step_eager issues the same launches without the graph.
  */
 int rlbm_batch_step(rlbm_batch b, int nsteps);
 int rlbm_batch_step_eager(rlbm_batch b, int nsteps);
@@ -304,11 +306,25 @@ int rlbm_batch_set_mode(rlbm_batch b, int mode);
 int rlbm_batch_get_mode(rlbm_batch b, int* mode);
 
 /*
+ * Work-group order of the push-kernel problems: work-groups run through
+ * groups of `bands` bands of 4 grid rows column by column (1..64; 0 = built-in
+ * choice, 2).  Only the order in which the hardware meets the work-groups
+ * changes (how long an upwind row stays in the L2), so results are identical
+ * bit for bit for every value.  Takes effect at the next step (descriptors
+ * and graph are rebuilt then, outside the timed region of
+ * rlbm_batch_step_timed).
+ */
+int rlbm_batch_set_push_bands(rlbm_batch b, int bands);
+int rlbm_batch_get_push_bands(rlbm_batch b, int* bands);
+
+/*
  * Autotuner: time `steps` graph-replayed steps for each candidate shape
- * (waves per work-group) in both launch modes, keep the fastest pair and
- * report its shape (rlbm_batch_get_mode gives its mode); the populations are
- * saved before and restored after, so the state is unchanged.  Allocates a
- * temporary copy of the populations.
+ * (waves per work-group) in both launch modes and keep the fastest pair;
+ * then, when the batch holds push-kernel problems, time the band groupings
+ * 1, 2, 4 and 8 with that pair and keep the fastest.  Reports the shape and
+ * the best time (rlbm_batch_get_mode and rlbm_batch_get_push_bands give the
+ * rest); the populations are saved before and restored after, so the state
+ * is unchanged.  Allocates a temporary copy of the populations.
  */
 int rlbm_batch_autotune(rlbm_batch b, const int* candidates, int ncand, int steps, int* best_waves, double* best_ms);
 

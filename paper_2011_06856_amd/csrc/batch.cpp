@@ -18,12 +18,15 @@ struct rlbm_batch_s {
     std::vector<int> tile_ix, push_ix;
     void* d_pdesc = nullptr;     // push descriptors
     int push_wgs = 0;
+    int push_bands = 0;          // bands of 4 rows per work-group group of the push part (0: default)
+    int desc_bands = -1;         // band grouping the push descriptors were built for
+    int graph_bands = -1;        // band grouping the graph was captured for
     std::string err;
     int prec = RLBM_F32, nmax = 3, max_np = 1, waves = 0, grid = 0;
     hipStream_t st = nullptr;
     bool own_stream = false;     // created here: graphs cannot capture the null stream
     BatchDesc* d_desc = nullptr;
-    int* d_counters = nullptr;   // 8 counters, 64 bytes apart
+    int* d_counters = nullptr;   // 8 range counters and the exit count, 64 bytes apart
     int* d_bounds = nullptr;     // 9 range bounds of the item list
     int parity = 0;              // buffer holding the current populations
     int total_items = 0;
@@ -57,6 +60,7 @@ void drop_graph(rlbm_batch b)
     b->graph = nullptr;
     b->graph_waves = -1;
     b->graph_mode = -1;
+    b->graph_bands = -1;
 }
 
 int effective_waves(rlbm_batch b)
@@ -68,9 +72,14 @@ int effective_waves(rlbm_batch b)
     return default_waves(b->prec, b->nmax, nv);
 }
 
-// Upload the descriptors for a work-group shape (chunk sizes depend on it).
+int effective_bands(rlbm_batch b) { return b->push_bands ? b->push_bands : RLBM_PUSH_BANDS; }
+
+// Upload the descriptors for a work-group shape (chunk sizes depend on it),
+// once no launch on the batch's stream reads them any more.
 int upload_descs(rlbm_batch b, int waves)
 {
+    hipError_t se = hipStreamSynchronize(b->st);
+    if (se != hipSuccess) return bhip(b, se, "sync");
     std::vector<BatchDesc> d(b->tile_ix.size());
     int item = 0;
     for (size_t i = 0; i < b->tile_ix.size(); ++i) {
@@ -98,9 +107,8 @@ int upload_descs(rlbm_batch b, int waves)
     return RLBM_OK;
 }
 
-// One step.  Persistent mode: reset the 8 work counters (a small kernel, not
-// a memset node, so that the sequence can be captured in a graph) and run the
-// persistent step.  Flat mode: one work-group per item.
+// One step.  Persistent mode: the persistent step (its work counters are zero
+// on entry and left at zero).  Flat mode: one work-group per item.
 // Then the push-kernel problems in one flat launch.
 hipError_t enqueue_step(rlbm_batch b, int waves, int parity)
 {
@@ -111,10 +119,8 @@ hipError_t enqueue_step(rlbm_batch b, int waves, int parity)
             e = launch_batch_flat(b->prec, b->nmax, waves, b->total_items, b->d_desc, nt, parity, b->ctx[0]->d_Pc,
                                   b->max_np, b->st);
         } else {
-            e = launch_reset_counters(b->d_counters, b->st);
-            if (e == hipSuccess)
-                e = launch_batch_step(b->prec, b->nmax, waves, b->grid, b->d_desc, nt, b->d_counters, b->d_bounds,
-                                      parity, b->ctx[0]->d_Pc, b->max_np, b->st);
+            e = launch_batch_step(b->prec, b->nmax, waves, b->grid, b->d_desc, nt, b->d_counters, b->d_bounds,
+                                  parity, b->ctx[0]->d_Pc, b->max_np, b->st);
         }
     }
     if (e == hipSuccess && !b->push_ix.empty())
@@ -123,7 +129,8 @@ hipError_t enqueue_step(rlbm_batch b, int waves, int parity)
 }
 
 // Push-kernel problems: tables, partial-sum buffers and the partial sums of
-// the current populations (outside any graph capture), then descriptors.
+// the current populations (outside any graph capture), then descriptors for
+// the current band grouping.
 int prepare_push(rlbm_batch b)
 {
     if (b->push_ix.empty()) return RLBM_OK;
@@ -135,9 +142,15 @@ int prepare_push(rlbm_batch b)
         if (rc != RLBM_OK) return bfail(b, rc, "push kernel setup: " + err);
         cs.push_back(c);
     }
-    if (!b->d_pdesc) {
-        const int rc = push_batch_descs(cs, &b->d_pdesc, &b->push_wgs);
+    const int bands = effective_bands(b);
+    if (!b->d_pdesc || b->desc_bands != bands) {
+        drop_graph(b);
+        hipError_t e = hipStreamSynchronize(b->st);   // no step in flight reads the old descriptors
+        if (e != hipSuccess) return bhip(b, e, "sync");
+        b->desc_bands = -1;
+        const int rc = push_batch_descs(cs, bands, &b->d_pdesc, &b->push_wgs);
         if (rc != RLBM_OK) return bfail(b, rc, "push descriptors");
+        b->desc_bands = bands;
     }
     return RLBM_OK;
 }
@@ -165,6 +178,7 @@ int build_graph(rlbm_batch b, int waves)
     }
     b->graph_waves = waves;
     b->graph_mode = b->mode;
+    b->graph_bands = b->desc_bands;
     return RLBM_OK;
 }
 
@@ -177,7 +191,7 @@ void set_parity(rlbm_batch b, int parity)
 
 int step_impl(rlbm_batch b, int nsteps, int use_graph)
 {
-    if (nsteps > 0) {
+    {   // also for nsteps = 0: a graph captured now must hold the push launch
         const int rc = prepare_push(b);
         if (rc != RLBM_OK) return rc;
     }
@@ -188,7 +202,7 @@ int step_impl(rlbm_batch b, int nsteps, int use_graph)
         if (rc != RLBM_OK) return rc;
         b->desc_waves = waves;
     }
-    if (use_graph && (b->graph_waves != waves || b->graph_mode != b->mode)) {
+    if (use_graph && (b->graph_waves != waves || b->graph_mode != b->mode || b->graph_bands != b->desc_bands)) {
         const int rc = build_graph(b, waves);
         if (rc != RLBM_OK) return rc;
     }
@@ -261,9 +275,9 @@ int rlbm_batch_create(rlbm_batch* out, const rlbm_problem* probs, int count, int
     for (int i = 0; i < count; ++i)
         (resolve_kernel(b->ctx[i]) == RLBM_KERNEL_PUSH ? b->push_ix : b->tile_ix).push_back(i);
     hipError_t e = hipMalloc(&b->d_desc, sizeof(BatchDesc) * count);
-    if (e == hipSuccess) e = hipMalloc(&b->d_counters, 8 * 16 * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&b->d_counters, 9 * 16 * sizeof(int));
     if (e == hipSuccess) e = hipMalloc(&b->d_bounds, 16 * sizeof(int));
-    if (e == hipSuccess) e = hipMemset(b->d_counters, 0, 8 * 16 * sizeof(int));
+    if (e == hipSuccess) e = hipMemset(b->d_counters, 0, 9 * 16 * sizeof(int));
     if (e == hipSuccess) e = hipEventCreate(&b->ev0);
     if (e == hipSuccess) e = hipEventCreate(&b->ev1);
     if (e != hipSuccess) {
@@ -345,9 +359,14 @@ int rlbm_batch_autotune(rlbm_batch b, const int* candidates, int ncand, int step
         else if (hipMemcpy(saved[i], b->ctx[i]->f[parity0], bytes, hipMemcpyDeviceToDevice) != hipSuccess)
             rc = bfail(b, RLBM_EDEVICE, "autotune backup copy");
     }
-    const int keep = b->waves, keep_mode = b->mode;
-    int bw = 0, bm = keep_mode;
+    const int keep = b->waves, keep_mode = b->mode, keep_bands = b->push_bands;
+    int bw = 0, bm = keep_mode, bb = keep_bands;
     double bms = 1e300;
+    auto trial = [&](double* ms) {
+        return step_impl(b, 2, 1) == RLBM_OK &&   // warm-up, graph build
+               rlbm_batch_step_timed(b, steps, ms) == RLBM_OK;
+    };
+    // the tile-kernel part: work-group shape and launch mode
     for (int k = 0; k < ncand && rc == RLBM_OK; ++k)
         for (int mode = RLBM_BATCH_PERSISTENT; mode <= RLBM_BATCH_FLAT; ++mode) {
             const int w = candidates[k];
@@ -355,14 +374,27 @@ int rlbm_batch_autotune(rlbm_batch b, const int* candidates, int ncand, int step
             b->waves = w;
             b->mode = mode;
             double ms = 0.0;
-            if (step_impl(b, 2, 1) != RLBM_OK) continue;   // warm-up, graph build
-            if (rlbm_batch_step_timed(b, steps, &ms) != RLBM_OK) continue;
+            if (!trial(&ms)) continue;
             if (ms < bms) {
                 bms = ms;
                 bw = w;
                 bm = mode;
             }
         }
+    // the push part, with that shape: bands of 4 rows per work-group group
+    if (bw && !b->push_ix.empty() && rc == RLBM_OK) {
+        b->waves = bw;
+        b->mode = bm;
+        for (int sb : {1, 2, 4, 8}) {
+            b->push_bands = sb;
+            double ms = 0.0;
+            if (!trial(&ms)) continue;
+            if (ms < bms) {
+                bms = ms;
+                bb = sb;
+            }
+        }
+    }
     for (size_t i = 0; i < b->ctx.size(); ++i) {
         if (saved[i]) {
             size_t bytes = 0;
@@ -374,20 +406,32 @@ int rlbm_batch_autotune(rlbm_batch b, const int* candidates, int ncand, int step
     }
     set_parity(b, parity0);
     for (int i : b->push_ix) b->ctx[i]->pvalid = 0;   // populations restored: rebuild their partial sums
-    if (rc != RLBM_OK) {
+    if (rc != RLBM_OK || !bw) {
         b->waves = keep;
         b->mode = keep_mode;
-        return rc;
-    }
-    if (!bw) {
-        b->waves = keep;
-        b->mode = keep_mode;
-        return bfail(b, RLBM_EDEVICE, "no candidate shape ran");
+        b->push_bands = keep_bands;
+        return rc != RLBM_OK ? rc : bfail(b, RLBM_EDEVICE, "no candidate shape ran");
     }
     b->waves = bw;
     b->mode = bm;
+    b->push_bands = bb;
     if (best_waves) *best_waves = bw;
     if (best_ms) *best_ms = bms;
+    return RLBM_OK;
+}
+
+int rlbm_batch_set_push_bands(rlbm_batch b, int bands)
+{
+    if (!b) return RLBM_EINVAL;
+    if (bands < 0 || bands > 64) return bfail(b, RLBM_EINVAL, "bands must be in [0, 64]");
+    b->push_bands = bands;
+    return RLBM_OK;
+}
+
+int rlbm_batch_get_push_bands(rlbm_batch b, int* bands)
+{
+    if (!b || !bands) return RLBM_EINVAL;
+    *bands = effective_bands(b);
     return RLBM_OK;
 }
 

@@ -361,7 +361,9 @@ __global__ __launch_bounds__(1024) void k_stream_collide(const TS* __restrict__ 
 // ranges, one per XCD; a work-group takes items from its own XCD's range
 // through an atomic counter (neighbouring rows stay in that XCD's L2) and,
 // once it is drained, from the other ranges in turn.  Every work-group leaves
-// when all ranges are drained.
+// when all ranges are drained; the last one to leave (counted in
+// counters[8 * 16]) sets the 9 counters back to zero for the next launch, so
+// a step is this one launch.
 template <typename TS, typename TC, int NM, int VPT>
 __global__ __launch_bounds__(1024) void k_batch_step(const BatchDesc* __restrict__ descs, int nprob,
                                                      int* __restrict__ counters, const int* __restrict__ bounds,
@@ -396,6 +398,10 @@ __global__ __launch_bounds__(1024) void k_batch_step(const BatchDesc* __restrict
             __syncthreads();
         }
     }
+    // Every atomic this work-group makes on the range counters has returned
+    // before its exit is counted, so the last work-group out sees them all.
+    if (threadIdx.x == 0 && atomicAdd(&counters[8 * 16], 1) == (int)gridDim.x - 1)
+        for (int k = 0; k <= 8; ++k) atomicExch(&counters[k * 16], 0);
 }
 
 // Batched form, flat launch: one work-group per (problem, tile) item, no work
@@ -417,11 +423,6 @@ __global__ __launch_bounds__(1024) void k_batch_flat(const BatchDesc* __restrict
     sc_tile<TS, TC, NM, VPT>(static_cast<const TS*>(D.f[parity]), static_cast<TS*>(D.f[parity ^ 1]),
                              static_cast<const SRec<TC>*>(P.srec), static_cast<const CRec<TC, NM>*>(P.crec), P.G, Pc,
                              P, item - D.item0, smem);
-}
-
-__global__ void k_reset_counters(int* counters)
-{
-    if (threadIdx.x < 8) counters[threadIdx.x * 16] = 0;
 }
 
 // Initial populations: the truncated equilibrium of given fields, one thread
@@ -532,12 +533,8 @@ hipError_t launch_sc_t(int waves, const SCParams& p, hipStream_t st)
 // Held values per lane, by storage precision and order class: the register
 // budget (128 VGPRs at 16 waves per work-group) is shared with the FP64
 // coefficient evaluation, whose size grows with the order.
-#ifndef RLBM_VPT_F32_HI
 #define RLBM_VPT_F32_HI 48
-#endif
-#ifndef RLBM_VPT_F32_LO
 #define RLBM_VPT_F32_LO 64
-#endif
 template <typename TC, int NM>
 struct Vpt {
     static constexpr int value =
@@ -697,12 +694,6 @@ int batch_grid(int prec, int nmax, int waves, int max_np)
     }
 #undef RLBM_GRID_CASE
     return 0;
-}
-
-hipError_t launch_reset_counters(int* counters, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, st, counters);
-    return hipGetLastError();
 }
 
 namespace {

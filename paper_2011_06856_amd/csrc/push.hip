@@ -155,12 +155,9 @@ struct PushParams {
     int* flag;
 };
 
-// Work-group order of the push kernel: groups of RLBM_PUSH_SB bands of 4
-// rows are taken column by column, so that vertically adjacent work-groups
-// (whose boundary rows are each other's upwind rows) run at the same time.
-#ifndef RLBM_PUSH_SB
-#define RLBM_PUSH_SB 2
-#endif
+// Work-group order of the push kernel: groups of P.sb bands of 4 rows are
+// taken column by column, so that vertically adjacent work-groups (whose
+// boundary rows are each other's upwind rows) run at the same time.
 
 // Band (of 4 rows) and tile column of work-group b in that order.
 __device__ __forceinline__ void push_wg_tile(int b, int ntx, int ny, int sb, int& band, int& col)
@@ -174,9 +171,7 @@ __device__ __forceinline__ void push_wg_tile(int b, int ntx, int ny, int sb, int
 }
 
 // Scalar-cache prefetch distance of the push kernel, in load batches (0: off).
-#ifndef RLBM_PUSH_PREFETCH
 #define RLBM_PUSH_PREFETCH 2
-#endif
 
 constexpr int NMOM = 8;     // N^0 N^x N^y T^00 T^0x T^0y T^xx T^xy
 
@@ -304,7 +299,6 @@ __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __rest
     CAddr* const adr = (CAddr*)P.paddr;
     using CSeg = const PUSH_CONST_AS PSeg;
     using CDbl = const PUSH_CONST_AS double;
-    using CTab = const PUSH_CONST_AS T;
     CRec* const rec = (CRec*)P.prec;
     CSeg* const seg = (CSeg*)P.seg;
     CDbl* const Gtab = (CDbl*)P.G;
@@ -477,7 +471,15 @@ __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __rest
 #pragma unroll
                 for (int j = 0; j < 9; ++j) Sm[j] = 0.0;
                 const int v0 = G.begin;
+                const unsigned osb = sx > 0 ? omb : opb;   // to the upwind column (edge tiles)
                 for (int kb = 0; kb < G.nbatch; ++kb) {
+                    // the lanes' byte offsets, made opaque once per batch: each
+                    // load and store is then addressed as a scalar base plus a
+                    // 32-bit lane offset, with no 64-bit vector address
+                    // arithmetic (hoisting base + offset out of the loop would
+                    // keep the sums in vector registers)
+                    unsigned oc = ocb, os = osb;
+                    asm volatile("" : "+v"(oc), "+v"(os));
                     T Sb[9];
 #pragma unroll
                     for (int j = 0; j < 9; ++j) Sb[j] = T(0);
@@ -502,16 +504,15 @@ __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __rest
                         CAddr& A = adr[v0 + kb * LB + b];
                         const char* p0 = inb + A.roff;
                         if (INIT) {
-                            raw[b][0] = ld(p0, ocb);
+                            raw[b][0] = ld(p0, oc);
                         } else {
                             const char* p1 = p0 + (A.sy > 0 ? dmb : dpb);
                             if (FAST) {
-                                raw[b][0] = ld(p0, ocb); raw[b][1] = ld(p0 + A.dx, ocb);
-                                raw[b][2] = ld(p1, ocb); raw[b][3] = ld(p1 + A.dx, ocb);
+                                raw[b][0] = ld(p0, oc); raw[b][1] = ld(p0 + A.dx, oc);
+                                raw[b][2] = ld(p1, oc); raw[b][3] = ld(p1 + A.dx, oc);
                             } else {
-                                const unsigned osb = A.dx < 0 ? omb : opb;
-                                raw[b][0] = ld(p0, ocb); raw[b][1] = ld(p0, osb);
-                                raw[b][2] = ld(p1, ocb); raw[b][3] = ld(p1, osb);
+                                raw[b][0] = ld(p0, oc); raw[b][1] = ld(p0, os);
+                                raw[b][2] = ld(p1, oc); raw[b][3] = ld(p1, os);
                             }
                         }
                     }
@@ -535,7 +536,7 @@ __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __rest
                             const unsigned rv = srseed + (unsigned)(v0 + kb * LB + b) * 0x9e3779b9u;
                             const ST gq = to_st<ST, T>(om1 * (gs + dv), rv);
                             fnew = st_to<T, ST>(gq);   // the stored value feeds the partial sums
-                            ST* dst = reinterpret_cast<ST*>(outb + Rr.woff + ocb);
+                            ST* dst = reinterpret_cast<ST*>(outb + Rr.woff + oc);
                             if (FAST || active) __builtin_nontemporal_store(gq, dst);
                         } else {
                             const T f = Rr.w[0] * raw[b][0] + Rr.w[1] * raw[b][1] + Rr.w[2] * raw[b][2] +
@@ -546,7 +547,7 @@ __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __rest
                             const T om = a0 - ax * Rr.cth - ay * Rr.sth;
                             fnew = f + om * (feq - f);
                             // non-temporal: the next read of this plane is a step away
-                            T* dst = reinterpret_cast<T*>(outb + Rr.woff + ocb);
+                            T* dst = reinterpret_cast<T*>(outb + Rr.woff + oc);
                             if (FAST || active) __builtin_nontemporal_store(fnew, dst);
                         }
                         // explicit FMAs: the step and the rebuild (INIT) must
@@ -654,12 +655,9 @@ __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __rest
     }
 }
 
-#ifndef RLBM_PUSH_WPE
+// Minimum work-groups per execution unit, and the load batch of FP32.
 #define RLBM_PUSH_WPE 1
-#endif
-#ifndef RLBM_PUSH_LB_F32
 #define RLBM_PUSH_LB_F32 8
-#endif
 
 template <typename T, typename ST, int NM, int LB, bool INIT, bool DEV>
 __global__ __launch_bounds__(256, RLBM_PUSH_WPE) void k_push_step(const ST* __restrict__ fin, ST* __restrict__ fout,
@@ -958,7 +956,7 @@ PushParams make_push_params(rlbm_ctx c)
     P.nx = c->nx; P.ny = c->ny; P.Np = c->q.Np; P.bcx = c->bcx; P.bcy = c->bcy;
     P.ntiles = ((c->nx + 63) / 64) * c->ny;
     P.nrec = c->pnrec;
-    P.sb = RLBM_PUSH_SB;
+    P.sb = RLBM_PUSH_BANDS;
     P.S = c->S;
     P.rate = c->rate;
     P.dt = c->dt;
@@ -1001,8 +999,7 @@ hipError_t launch_push(rlbm_ctx c, bool init)
 // Batched form.  push_prepare: tables and buffers of a push-kernel problem,
 // and its partial sums for the current populations (pcur = cur), issued on
 // the context's stream.  push_batch_wgs: its work-groups per step.
-// push_batch_descs: the device descriptors of a list of problems (device
-// array, nprob entries, allocated here; free with hipFree).
+// push_batch_descs: the device descriptors of a list of problems.
 int push_prepare(rlbm_ctx c, std::string& err)
 {
     if (!c->d_prec) {
@@ -1023,7 +1020,7 @@ int push_prepare(rlbm_ctx c, std::string& err)
 
 int push_batch_wgs(rlbm_ctx c) { return ((c->nx + 63) / 64) * ((c->ny + 3) / 4); }
 
-int push_batch_descs(const std::vector<rlbm_ctx>& cs, void** d_descs, int* total_wgs)
+int push_batch_descs(const std::vector<rlbm_ctx>& cs, int bands, void** d_descs, int* total_wgs)
 {
     std::vector<PushDesc> d(cs.size());
     int wg = 0;
@@ -1034,14 +1031,17 @@ int push_batch_descs(const std::vector<rlbm_ctx>& cs, void** d_descs, int* total
         d[i].pp[0] = c->pp[0];
         d[i].pp[1] = c->pp[1];
         d[i].P = make_push_params(c);
+        if (bands > 0) d[i].P.sb = bands;
         d[i].wg0 = wg;
         d[i].wgs = push_batch_wgs(c);
         wg += d[i].wgs;
     }
     *total_wgs = wg;
-    *d_descs = nullptr;
     if (d.empty()) return RLBM_OK;
-    if (hipMalloc(d_descs, d.size() * sizeof(PushDesc)) != hipSuccess) return RLBM_ENOMEM;
+    if (!*d_descs && hipMalloc(d_descs, d.size() * sizeof(PushDesc)) != hipSuccess) {
+        *d_descs = nullptr;
+        return RLBM_ENOMEM;
+    }
     if (hipMemcpy(*d_descs, d.data(), d.size() * sizeof(PushDesc), hipMemcpyHostToDevice) != hipSuccess)
         return RLBM_EDEVICE;
     return RLBM_OK;

@@ -68,9 +68,7 @@ struct alignas(16) CRec {
 };
 
 // Velocities per load batch and the padding of the velocity tables.
-#ifndef RLBM_LB
 #define RLBM_LB 8
-#endif
 #define RLBM_VPAD (RLBM_LB * 16)
 
 // Host-side quadrature and coefficient tables (FP64).
@@ -378,13 +376,14 @@ struct SCParams {
 };
 
 // Velocity count from which RLBM_KERNEL_AUTO selects the push kernel.
-#ifndef RLBM_PUSH_MIN_NVEL
 #define RLBM_PUSH_MIN_NVEL 320
-#endif
 
-#ifndef RLBM_BAND_DEFAULT
+// Tile order of the tile kernel: rows per band.
 #define RLBM_BAND_DEFAULT 1
-#endif
+
+// Work-group order of the push kernel: bands of 4 rows per group (a batch
+// may choose another value).
+#define RLBM_PUSH_BANDS 2
 
 // One problem of a batch: its buffers, tables and step parameters, and the
 // index of its first work item.
@@ -489,10 +488,11 @@ void* scratch_ptr(int dev);
 long long scratch_max_sites();
 hipError_t launch_fields_charges(int prec, const void* f, const VelRec<double>* vel, double* out, double* partials,
                                  double* charges, int* flag, int nx, int ny, int nvel, hipStream_t st);
+// Persistent batch step: counters = 9 ints, 16 apart (8 range counters and
+// the exit count), zero on entry and left at zero by the launch.
 hipError_t launch_batch_step(int prec, int nmax, int waves, int grid, const BatchDesc* descs, int nprob,
                              int* counters, const int* bounds, int parity, const double* Pc, int max_np,
                              hipStream_t st);
-hipError_t launch_reset_counters(int* counters, hipStream_t st);
 hipError_t launch_batch_flat(int prec, int nmax, int waves, int items, const BatchDesc* descs, int nprob, int parity,
                              const double* Pc, int max_np, hipStream_t st);
 
@@ -510,7 +510,10 @@ size_t push_partial_bytes(int prec, int nx, int ny);
 hipError_t launch_push(rlbm_ctx c, bool init);
 int push_prepare(rlbm_ctx c, std::string& err);
 int push_batch_wgs(rlbm_ctx c);
-int push_batch_descs(const std::vector<rlbm_ctx>& cs, void** d_descs, int* total_wgs);
+// Descriptors of the push-kernel problems of a batch, with `bands` bands of
+// 4 rows per work-group group (0: RLBM_PUSH_BANDS).  *d_descs is allocated
+// here when null (cs.size() entries; free with hipFree), else overwritten.
+int push_batch_descs(const std::vector<rlbm_ctx>& cs, int bands, void** d_descs, int* total_wgs);
 hipError_t launch_push_batch(int prec, int nmax, const void* d_descs, int nprob, int total_wgs, int parity,
                              hipStream_t st);
 // Copy the fields in d_fields (computed by launch_fields) and the charges to

@@ -53,6 +53,6 @@ timeout -s KILL 180 rocprofv3 --kernel-trace --stats -d $D/stats -o run --output
     python3 -m paper_2011_06856_amd.profile_run --workload batch48 --steps 40 > $D.out.txt
 python3 -m paper_2011_06856_amd.profile_summary --stats $D/stats --name batch_step_f32_batch48 \
     --kernel k_batch_step --launch-bytes 0 --out-dir $OUT \
-    --step-kernels k_batch_step,k_batch_flat,k_push_batch,k_reset_counters --steps 40 --sv-per-step $SV \
+    --step-kernels k_batch_step,k_batch_flat,k_push_batch --steps 40 --sv-per-step $SV \
     --command "rocprofv3 --kernel-trace --stats -- python3 -m paper_2011_06856_amd.profile_run --workload batch48 --steps 40 (bash paper_2011_06856_amd/profile_all.sh)"
 { echo; echo "Program output: \`$(grep profile_run: $D.out.txt)\`"; } >> $OUT/batch_step_f32_batch48.md

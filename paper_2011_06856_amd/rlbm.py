@@ -56,6 +56,8 @@ SIGNATURES = [
     ("rlbm_batch_step_timed", ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     ("rlbm_batch_set_waves", ctypes.c_int, [_vp, ctypes.c_int]),
     ("rlbm_batch_get_waves", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
+    ("rlbm_batch_set_push_bands", ctypes.c_int, [_vp, ctypes.c_int]),
+    ("rlbm_batch_get_push_bands", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
     ("rlbm_batch_set_mode", ctypes.c_int, [_vp, ctypes.c_int]),
     ("rlbm_batch_get_mode", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
     ("rlbm_batch_autotune", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int,
@@ -405,9 +407,20 @@ class Batch:
         self._check(lib().rlbm_batch_get_mode(self._h, ctypes.byref(m)))
         return {v: k for k, v in self.MODES.items()}[m.value]
 
+    def set_push_bands(self, bands):
+        """Work-group order of the push-kernel problems: bands of 4 rows per
+        group (0: the built-in choice); results do not depend on it."""
+        self._check(lib().rlbm_batch_set_push_bands(self._h, int(bands)))
+
+    def get_push_bands(self):
+        v = ctypes.c_int()
+        self._check(lib().rlbm_batch_get_push_bands(self._h, ctypes.byref(v)))
+        return v.value
+
     def autotune(self, candidates=(2, 3, 4, 6, 8), steps=6, cache=None, key=None):
-        """Pick the fastest work-group shape and launch mode; with `cache` (a
-        JSON file path) and `key`, reuse a stored choice or store the new one."""
+        """Pick the fastest work-group shape and launch mode, then the push
+        part's band grouping; with `cache` (a JSON file path) and `key`,
+        reuse a stored choice or store the new one."""
         import json
         if cache and key and os.path.exists(cache):
             try:
@@ -415,6 +428,7 @@ class Batch:
                 if key in d:
                     self.set_waves(d[key]["waves"])
                     self.set_mode(d[key].get("mode", "persistent"))
+                    self.set_push_bands(d[key].get("push_bands", 0))
                     return d[key]["waves"], d[key]["ms"]
             except (ValueError, KeyError):
                 pass
@@ -429,7 +443,8 @@ class Batch:
                     d = json.load(open(cache))
                 except ValueError:
                     d = {}
-            d[key] = {"waves": bw.value, "mode": self.get_mode(), "ms": bms.value}
+            d[key] = {"waves": bw.value, "mode": self.get_mode(), "push_bands": self.get_push_bands(),
+                      "ms": bms.value}
             json.dump(d, open(cache, "w"), indent=1)
         return bw.value, bms.value
 

@@ -144,3 +144,54 @@ def test_batch_with_push_kernel_problems_equals_single_runs_bitwise():
                 s.set_waves(waves)
                 s.step(5)
                 assert np.array_equal(b.problem(i).get_populations(), s.get_populations()), (prec, mode, i)
+
+
+def _push_mix(seed):
+    probs = small_problems(seed, count=4)
+    for i, K in ((0, 96), (2, 112)):        # 384 and 448 velocities: push kernel
+        probs[i] = dict(probs[i], K=K)
+    return probs
+
+
+def test_push_band_grouping_and_mode_changes_are_bitwise_neutral():
+    """The band grouping of the push part only reorders work-groups, and the
+    persistent launch leaves its work counters at zero: changing either
+    between steps, and timing the first steps, leaves every problem on the
+    trajectory it has when stepped alone."""
+    rl = _rlbm()
+    probs = _push_mix(6)
+    b = rl.Batch(probs)
+    assert b.get_push_bands() == 2
+    b.set_push_bands(1)
+    assert b.get_push_bands() == 1
+    waves = b.get_waves()
+    say("push bands: fresh batch, first call timed")
+    assert b.step_timed(3) > 0           # the graph of the first call holds the push launch
+    for bands, mode, n in ((8, "flat", 2), (3, "persistent", 3), (0, "persistent", 1), (4, "flat", 1)):
+        say("push bands=%d mode=%s steps=%d" % (bands, mode, n))
+        b.set_push_bands(bands)
+        b.set_mode(mode)
+        b.step(n)
+    total = 3 + 2 + 3 + 1 + 1
+    for i, p in enumerate(probs):
+        s = rl.Solver(p["Np"], p["K"], p["N"]).init_fields(p["nx"], p["ny"], *p["fields"], tau=p["tau"],
+                                                           dt=p["dt"], precision="f32")
+        s.set_waves(waves)
+        s.step(total)
+        assert np.array_equal(b.problem(i).get_populations(), s.get_populations()), i
+
+
+def test_autotune_with_push_problems_picks_bands_and_keeps_state():
+    rl = _rlbm()
+    probs = _push_mix(7)
+    b = rl.Batch(probs)
+    b.step(2)
+    before = [b.problem(i).get_populations().copy() for i in range(len(b))]
+    w, ms = b.autotune(candidates=(2, 4), steps=3)
+    assert w in (2, 4) and ms > 0 and b.get_push_bands() in (1, 2, 4, 8)
+    for i in range(len(b)):
+        assert np.array_equal(b.problem(i).get_populations(), before[i]), i
+    with pytest.raises(rl.RlbmError):
+        b.set_push_bands(-1)
+    with pytest.raises(rl.RlbmError):
+        b.set_push_bands(65)
