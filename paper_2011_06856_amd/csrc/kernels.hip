@@ -273,7 +273,12 @@ __device__ __forceinline__ void sc_tile(const TS* __restrict__ fin, TS* __restri
     // 3. equilibrium coefficients per shell, shells dealt to waves
     for (int i = w; i < P.Np; i += NW) {
         TC* ci = coef + i * NT * 64 + lane;
-        shell_coeffs<NM>(Gtab + (size_t)i * GS, Pc, fr.n, fr.T, fr.U0, fr.Ux, fr.Uy,
+        // the frame as opaque values: the shell-independent FP64 factors
+        // are then not hoisted out of the shell loop and held (register
+        // spills at order 7 otherwise)
+        double sn = fr.n, sT = fr.T, sU0 = fr.U0, sUx = fr.Ux, sUy = fr.Uy;
+        asm volatile("" : "+v"(sn), "+v"(sT), "+v"(sU0), "+v"(sUx), "+v"(sUy));
+        shell_coeffs<NM>(Gtab + (size_t)i * GS, Pc, sn, sT, sU0, sUx, sUy,
                          [&](int mm, double cm, double sm) __attribute__((always_inline)) {
                              if (!fr.ok) cm = sm = 0.0;
                              if (mm == 0) {
