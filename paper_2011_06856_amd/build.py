@@ -15,10 +15,6 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-result", "-Wno-unknown-warning-option"]
-# Per-source flags.  push.hip: matrix-core accumulators in ordinary vector
-# registers (the bfloat16 deviation step then keeps 2 waves per SIMD; in
-# accumulation registers they would add to the vector registers' count).
-SOURCE_FLAGS = {"push.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def build(verbose=False, out=SO):
@@ -28,7 +24,7 @@ def build(verbose=False, out=SO):
     jobs = []
     for src in SOURCES:
         obj = os.path.join(CSRC, src.rsplit(".", 1)[0] + "." + tag + ".o")
-        cmd = [HIPCC] + FLAGS + SOURCE_FLAGS.get(src, []) + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         jobs.append((cmd, obj))
     if verbose:
         for cmd, _ in jobs:

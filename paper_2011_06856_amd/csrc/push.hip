@@ -47,7 +47,6 @@
 // to the storage type (bfloat16: half the bytes of FP32).  The pushed partial
 // sums hold the moments of the full f_new = g_new + F_new: the F part of a
 // segment's monomial sums is sum_t C_t Y_t with per-segment tables Y.
-#include <array>
 #include <cstring>
 #include <new>
 #include <type_traits>
@@ -132,36 +131,8 @@ __device__ __forceinline__ unsigned fmix32(unsigned h)
     return h;
 }
 
-// Matrix-core operands of the bfloat16 deviation form (v_mfma_f32_32x32x16_bf16):
-// 8 bfloat16 per lane (A: row lane % 32, k 8 (lane / 32) + j; B: column
-// lane % 32, same k) and the 32 x 32 FP32 block, 16 values per lane (row
-// 8 (r / 4) + 4 (lane / 32) + r % 4, column lane % 32).
-typedef __bf16 mf_bf16x8 __attribute__((ext_vector_type(8)));
-typedef float mf_f32x16 __attribute__((ext_vector_type(16)));
-typedef unsigned mf_u32x4 __attribute__((ext_vector_type(4)));
-
-// Two floats as a bfloat16 pair (round to nearest even; a in the low half),
-// and a float pair split into high and low bfloat16 parts (a = hi + lo to
-// about 2^-16 relative).
-__device__ __forceinline__ unsigned pk_bf16(float a, float b)
-{
-    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
-    const b2 v = {(__bf16)a, (__bf16)b};
-    return __builtin_bit_cast(unsigned, v);
-}
-__device__ __forceinline__ void split_bf16(float a, float b, unsigned& hi, unsigned& lo)
-{
-    hi = pk_bf16(a, b);
-    lo = pk_bf16(a - __uint_as_float(hi << 16), b - __uint_as_float(hi & 0xffff0000u));
-}
-
-// Records per segment of the bfloat16 deviation form: whole groups of 32,
-// the velocity rows of one matrix-core block.
-constexpr int MF_GROUP = 32;
-
 // One segment: the velocities of shell i with upwind signs (sx, sy) of
-// quadrant q, padded with null records to whole load batches (bfloat16
-// deviations: to whole groups of MF_GROUP).
+// quadrant q, padded with null records to whole load batches.
 struct PSeg {
     int begin, nbatch;
     double p;
@@ -174,9 +145,6 @@ struct PushParams {
     const void* ytab;        // deviation storage: [4][Np][push_ys(NM)] (T), Y[q][i][t * 9 + j] = sum over the
                              // segment's velocities of H_t mono_j, mono = (1, c, s, c^2, c s, c^3, c^2 s,
                              // c^3 s, c^2 s^2); null otherwise
-    const void* hatab;       // bfloat16 deviations: [nrec / 32][KB][2][64] x 8 bfloat16, the A operand (rows:
-                             // the group's 32 velocities, k: harmonic t of the corner series, KB blocks of
-                             // 16) in high and low parts; null otherwise
     const double* G;
     const double* Pc;
     int nx, ny, Np, bcx, bcy, ntiles;
@@ -301,10 +269,7 @@ __device__ __forceinline__ void corner_series(AT al, AT be, LoadC loadc, AT* De)
 // slots and, for deviation storage, the site's equilibrium coefficients of
 // the current shell ([2 NM + 1][64]).
 __host__ __device__ constexpr int push_acc_entries() { return 96 + 3 * NMOM * 64; }
-__host__ __device__ constexpr int push_wlds(int NM, bool dev, bool mf = false)
-{
-    return push_acc_entries() + (dev ? (2 * NM + 1) * 64 : 0) + (mf ? MF_GROUP * 64 : 0);
-}
+__host__ __device__ constexpr int push_wlds(int NM, bool dev) { return push_acc_entries() + (dev ? (2 * NM + 1) * 64 : 0); }
 
 // Entries per segment of the deviation form's Y table as staged in LDS (the
 // 9 x (2 NM + 1) sums, padded to whole 16-byte rows).
@@ -329,10 +294,6 @@ __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __rest
     constexpr int NT = 2 * NM + 1;
     constexpr int NH = push_nh(NM, DEV);
     constexpr int GS = (RLBM_NMAX + 1) * (RLBM_NMAX + 1);
-    // bfloat16 deviations: the corner-series terms on the matrix cores, in
-    // KB blocks of 16 harmonics
-    constexpr bool MF = DEV && !INIT && sizeof(ST) == 2;
-    constexpr int KB = (NH + 15) / 16;
     using CRec = const PUSH_CONST_AS PRec<T, NH>;
     using CAddr = const PUSH_CONST_AS PAddr;
     CAddr* const adr = (CAddr*)P.paddr;
@@ -438,8 +399,6 @@ __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __rest
     // this wave's LDS after the halo accumulator, lane-contiguous
     T* const lrow = lh + 96;
     T* const lcc = lh + push_acc_entries();   // DEV: [2 NM + 1][64]
-    T* const ldv = lcc + NT * 64;              // MF: [MF_GROUP][64], a group's corner-series terms
-    const int mfw = 4 * (lane >> 5) * 64 + (lane & 31);   // MF: this lane's entry of the matrix-core block
     auto R = [&](int d, int k) __attribute__((always_inline)) -> T& { return lrow[(d * NMOM + k) * 64 + lane]; };
 #pragma unroll
     for (int d = 0; d < 3; ++d)
@@ -458,7 +417,16 @@ __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __rest
             // of the current state
             T cc[NT];
             if (!INIT) {
-                shell_coeffs<NM>(Gtab + (size_t)i * GS, Pc, fn_, fT, fU0, fUx, fUy,
+                // deviation storage: the frame as opaque values, once per
+                // shell.  Otherwise the compiler hoists the shell-independent
+                // FP64 factors of the coefficients (the polynomials in U^0)
+                // out of the shell loop and holds them through every velocity
+                // batch: about 60 more VGPRs, 2 waves per SIMD instead of 3.
+                // (The plain forms keep the hoisting: at 3 waves per SIMD
+                // they are where extra waves cost L2 reuse.)
+                double sn = fn_, sT = fT, sU0 = fU0, sUx = fUx, sUy = fUy;
+                if (DEV) asm volatile("" : "+v"(sn), "+v"(sT), "+v"(sU0), "+v"(sUx), "+v"(sUy));
+                shell_coeffs<NM>(Gtab + (size_t)i * GS, Pc, sn, sT, sU0, sUx, sUy,
                                  [&](int mm, double cm, double sm) __attribute__((always_inline)) {
                                      if (!ok) cm = sm = 0.0;
                                      if (mm == 0) {
@@ -504,29 +472,6 @@ __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __rest
 #pragma unroll
                     for (int t = 0; t < NT; ++t) D[t] -= lcc[t * 64 + lane];
                 }
-                // MF: the B operands of the matrix-core products, D_t of sites
-                // 0-31 (bh0, bl0) and 32-63 (bh1, bl1) in high and low bfloat16
-                // parts: each lane packs its own D_t of k 0-7 (x) and 8-15 (y)
-                // of a block, and one exchange of the halves gives lanes 32-63
-                // the 8-15 of sites 0-31 and lanes 0-31 the 0-7 of sites 32-63
-                mf_u32x4 bh0[KB], bl0[KB], bh1[KB], bl1[KB];
-                if constexpr (MF) {
-                    auto Dv = [&](int t) __attribute__((always_inline)) -> float { return t < NH ? (float)D[t] : 0.f; };
-#pragma unroll
-                    for (int k = 0; k < KB; ++k)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            unsigned xh, xl, yh, yl;
-                            split_bf16(Dv(16 * k + 2 * j), Dv(16 * k + 2 * j + 1), xh, xl);
-                            split_bf16(Dv(16 * k + 8 + 2 * j), Dv(16 * k + 9 + 2 * j), yh, yl);
-                            const auto sh = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
-                            const auto sl = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
-                            bh0[k][j] = sh[0];
-                            bh1[k][j] = sh[1];
-                            bl0[k][j] = sl[0];
-                            bl1[k][j] = sl[1];
-                        }
-                }
                 // sum f, f c, f s, f c^2, f c s, f c^3, f c^2 s, f c^3 s,
                 // f c^2 s^2 over the segment: each load batch's sums start from
                 // zero in T and are carried into FP64 (compensated: T rounds
@@ -536,9 +481,7 @@ __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __rest
                 for (int j = 0; j < 9; ++j) Sm[j] = 0.0;
                 const int v0 = G.begin;
                 const unsigned osb = sx > 0 ? omb : opb;   // to the upwind column (edge tiles)
-                // one load batch of LB velocities; dvsel(b): the corner-series
-                // term of velocity b from the matrix-core block (MF)
-                auto batch = [&](int kb, auto dvsel) __attribute__((always_inline)) {
+                for (int kb = 0; kb < G.nbatch; ++kb) {
                     // the lanes' byte offsets, made opaque once per batch: each
                     // load and store is then addressed as a scalar base plus a
                     // 32-bit lane offset, with no 64-bit vector address
@@ -593,14 +536,9 @@ __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __rest
                         } else if (DEV) {
                             const T gs = Rr.w[0] * raw[b][0] + Rr.w[1] * raw[b][1] + Rr.w[2] * raw[b][2] +
                                          Rr.w[3] * raw[b][3];
-                            T dv;
-                            if constexpr (MF) {
-                                dv = dvsel(b);
-                            } else {
-                                dv = D[0] * Rr.H[0];
+                            T dv = D[0] * Rr.H[0];
 #pragma unroll
-                                for (int t = 1; t < NH; ++t) dv += D[t] * Rr.H[t];
-                            }
+                            for (int t = 1; t < NH; ++t) dv += D[t] * Rr.H[t];
                             const T om1 = a0 + ax * Rr.cth + ay * Rr.sth;
                             // velocity v draws srseed + v phi (a Weyl sequence, phi
                             // the golden-ratio increment)
@@ -630,51 +568,6 @@ __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __rest
 #pragma unroll
                     for (int j = 0; j < 9; ++j) Sm[j] += (double)Sb[j];
                     if (RLBM_PUSH_PREFETCH > 0) asm volatile("" ::"s"(pf));
-                };
-                if constexpr (MF) {
-                    // groups of 32 velocities: their corner-series terms
-                    // sum_t D_t H_t for the wave's 64 sites as two 32 x 32 x 16
-                    // bfloat16 matrix-core products per k block (sites 0-31 and
-                    // 32-63), each as hi x hi + hi x lo + lo x hi with FP32
-                    // accumulation (about 2^-16 relative), staged in LDS for the
-                    // group's four load batches
-                    const mf_u32x4* ha = static_cast<const mf_u32x4*>(P.hatab) + (size_t)(v0 / MF_GROUP) * KB * 2 * 64 + lane;
-                    for (int kg = 0; kg < G.nbatch / 4; ++kg) {
-                        mf_f32x16 c0 = {}, c1 = {};
-#pragma unroll
-                        for (int k = 0; k < KB; ++k) {
-                            const mf_bf16x8 ah = __builtin_bit_cast(mf_bf16x8, ha[((kg * KB + k) * 2 + 0) * 64]);
-                            const mf_bf16x8 al = __builtin_bit_cast(mf_bf16x8, ha[((kg * KB + k) * 2 + 1) * 64]);
-                            const mf_bf16x8 h0 = __builtin_bit_cast(mf_bf16x8, bh0[k]), l0 = __builtin_bit_cast(mf_bf16x8, bl0[k]);
-                            const mf_bf16x8 h1 = __builtin_bit_cast(mf_bf16x8, bh1[k]), l1 = __builtin_bit_cast(mf_bf16x8, bl1[k]);
-                            c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, h0, c0, 0, 0, 0);
-                            c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, h1, c1, 0, 0, 0);
-                            c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, l0, c0, 0, 0, 0);
-                            c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, l1, c1, 0, 0, 0);
-                            c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, h0, c0, 0, 0, 0);
-                            c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, h1, c1, 0, 0, 0);
-                        }
-                        // to this wave's LDS as [velocity][site]: c0[r] and c1[r] are
-                        // velocity 8 (r / 4) + 4 (lane / 32) + r % 4 of sites
-                        // lane % 32 and 32 + lane % 32
-#pragma unroll
-                        for (int r = 0; r < 16; ++r) {
-                            ldv[(8 * (r / 4) + (r % 4)) * 64 + mfw] = c0[r];
-                            ldv[(8 * (r / 4) + (r % 4)) * 64 + mfw + 32] = c1[r];
-                        }
-                        // (no instruction moves between the batches: each keeps
-                        // its own loads in flight, as the plain loop does)
-                        __builtin_amdgcn_sched_barrier(0);
-                        batch(4 * kg + 0, [&](int b) -> T { return ldv[(0 + b) * 64 + lane]; });
-                        __builtin_amdgcn_sched_barrier(0);
-                        batch(4 * kg + 1, [&](int b) -> T { return ldv[(8 + b) * 64 + lane]; });
-                        __builtin_amdgcn_sched_barrier(0);
-                        batch(4 * kg + 2, [&](int b) -> T { return ldv[(16 + b) * 64 + lane]; });
-                        __builtin_amdgcn_sched_barrier(0);
-                        batch(4 * kg + 3, [&](int b) -> T { return ldv[(24 + b) * 64 + lane]; });
-                    }
-                } else {
-                    for (int kb = 0; kb < G.nbatch; ++kb) batch(kb, [](int) -> T { return T(0); });
                 }
                 // DEV: add the monomial sums of the equilibrium part F of the
                 // stored state, sum_t C_t Y_t (explicit FMAs, same order in
@@ -774,7 +667,6 @@ __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __rest
 // Minimum work-groups per execution unit, and the load batch of FP32.
 #define RLBM_PUSH_WPE 1
 #define RLBM_PUSH_LB_F32 8
-static_assert(MF_GROUP == 4 * RLBM_PUSH_LB_F32, "a matrix-core group is four FP32 load batches");
 
 template <typename T, typename ST, int NM, int LB, bool INIT, bool DEV>
 __global__ __launch_bounds__(256, RLBM_PUSH_WPE) void k_push_step(const ST* __restrict__ fin, ST* __restrict__ fout,
@@ -792,8 +684,7 @@ __global__ __launch_bounds__(256, RLBM_PUSH_WPE) void k_push_step(const ST* __re
     int band, col;
     push_wg_tile(b, ntx, P.ny, P.sb, band, col);
     const int ty = band * 4 + wv;
-    constexpr bool MFK = DEV && sizeof(ST) == 2;   // bfloat16 deviations: the LDS block of the matrix-core terms
-    T* const ylds = reinterpret_cast<T*>(psmem) + 4 * push_wlds(NM, DEV, MFK);
+    T* const ylds = reinterpret_cast<T*>(psmem) + 4 * push_wlds(NM, DEV);
     if (DEV) {
         // the work-group's copy of the Y table (read with broadcast LDS loads
         // in each segment's fold); the kernel's only barrier
@@ -805,7 +696,7 @@ __global__ __launch_bounds__(256, RLBM_PUSH_WPE) void k_push_step(const ST* __re
     if (ty >= P.ny) return;   // whole waves
     const bool live = true;
     const int tile = ty * ntx + col;
-    T* lh = reinterpret_cast<T*>(psmem) + (size_t)wv * push_wlds(NM, DEV, MFK);
+    T* lh = reinterpret_cast<T*>(psmem) + (size_t)wv * push_wlds(NM, DEV);
     push_tile<T, ST, NM, LB, INIT, DEV>(fin, fout, pin, pout, cin, cout, P, tile, lh, ylds, live);
 }
 
@@ -860,8 +751,7 @@ hipError_t launch_push_t(bool init, const void* fin, void* fout, const void* pin
     constexpr int LB = PushLB<T>::value;
     const unsigned blocks = (unsigned)(((P.nx + 63) / 64) * ((P.ny + 3) / 4));
     // 4 waves x (halo + row slots), and the Y table of the deviation form
-    constexpr bool MFK = DEV && sizeof(ST) == 2;
-    const size_t lds = ((size_t)4 * push_wlds(NM, DEV, MFK) + (DEV ? (size_t)4 * P.Np * push_ys(NM) : 0)) * sizeof(T);
+    const size_t lds = ((size_t)4 * push_wlds(NM, DEV) + (DEV ? (size_t)4 * P.Np * push_ys(NM) : 0)) * sizeof(T);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     if (lds > 64 * 1024) {   // beyond the default limit of dynamic LDS: opt in (set once per size)
         static size_t configured[2] = {0, 0};
@@ -892,22 +782,6 @@ hipError_t launch_push_batch_t(const void* descs, int nprob, int wgs, int parity
     return hipGetLastError();
 }
 
-// bfloat16 of a float, rounded to nearest even (finite values), and back.
-inline uint16_t bf16_rne(float f)
-{
-    uint32_t u;
-    std::memcpy(&u, &f, 4);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-inline float bf16_value(uint16_t h)
-{
-    const uint32_t u = (uint32_t)h << 16;
-    float f;
-    std::memcpy(&f, &u, 4);
-    return f;
-}
-
 // Tables of the push kernel: segment-ordered records (T arithmetic, ST
 // storage), and for deviation storage the per-segment monomial sums Y of
 // the equilibrium basis.
@@ -917,15 +791,9 @@ int upload_push_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, std::string
     constexpr int LB = PushLB<T>::value;
     constexpr int NT = 2 * NM + 1;
     constexpr int NH = push_nh(NM, DEV);
-    // bfloat16 deviations: segments in whole groups of MF_GROUP records, and
-    // the A operand table of the matrix-core corner series
-    constexpr bool MFH = DEV && sizeof(ST) == 2;
-    constexpr int PADV = MFH ? MF_GROUP : LB;
-    constexpr int KB = (NH + 15) / 16;
     const int Np = c->q.Np, K = c->q.K, nv = c->q.nvel;
     const long long S = c->S, es = (long long)sizeof(ST);
     std::vector<PRec<T, NH>> recs;
-    std::vector<std::array<double, NH>> hrows;   // MFH: each record's harmonic row (padding: zeros)
     std::vector<PAddr> adrs;
     std::vector<PSeg> segs(4 * (size_t)Np);
     std::vector<T> ytab;
@@ -960,11 +828,6 @@ int upload_push_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, std::string
                     H[2 * m] = c->q.w[v] * std::sin(m * c->q.theta[v]);
                 }
                 for (int t = 0; t < NH; ++t) A.H[t] = (T)H[t];
-                if (MFH) {
-                    std::array<double, NH> hr;
-                    for (int t = 0; t < NH; ++t) hr[t] = H[t];
-                    hrows.push_back(hr);
-                }
                 const double cs = R.cth, sn = R.sth;
                 A.cth = (T)cs; A.sth = (T)sn;
                 const double mono[9] = {1.0, cs, sn, cs * cs, cs * sn, cs * cs * cs, cs * cs * sn, cs * cs * cs * sn,
@@ -985,8 +848,7 @@ int upload_push_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, std::string
             if (DEV)
                 for (int t = 0; t < NT; ++t)
                     for (int k = 0; k < 9; ++k) ytab[(size_t)(q * Np + i) * push_ys(NM) + t * 9 + k] = (T)Y[t][k];
-            while (count % PADV) {
-                if (MFH) hrows.push_back(std::array<double, NH>{});
+            while (count % LB) {
                 PAddr nulla;
                 std::memset(&nulla, 0, sizeof(nulla));
                 if (!adrs.empty()) {
@@ -1001,7 +863,7 @@ int upload_push_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, std::string
             }
             G.nbatch = count / LB;
         }
-    if ((long long)recs.size() > 4LL * nv + 4LL * Np * PADV) {
+    if ((long long)recs.size() > 4LL * nv + 4LL * Np * LB) {
         err = "push table size";
         return RLBM_EINVAL;
     }
@@ -1022,29 +884,6 @@ int upload_push_t(rlbm_ctx c, const std::vector<VelRec<double>>& vd, std::string
     if (DEV) {
         if ((e = hipMalloc(&c->d_pytab, ytab.size() * sizeof(T))) != hipSuccess) return RLBM_ENOMEM;
         if ((e = hipMemcpy(c->d_pytab, ytab.data(), ytab.size() * sizeof(T), hipMemcpyHostToDevice)) != hipSuccess) {
-            err = hipGetErrorString(e);
-            return RLBM_EDEVICE;
-        }
-    }
-    if (MFH) {
-        // A operand of group g, block k, part (0 high, 1 low), lane l: the 8
-        // harmonics t = 16 k + 8 (l / 32) + j of record 32 g + l % 32, as
-        // bfloat16 (high part: H rounded; low part: the rest, rounded)
-        const size_t ng = recs.size() / MF_GROUP;
-        std::vector<uint16_t> ha(ng * KB * 2 * 64 * 8, 0);
-        for (size_t g = 0; g < ng; ++g)
-            for (int k = 0; k < KB; ++k)
-                for (int l = 0; l < 64; ++l)
-                    for (int j = 0; j < 8; ++j) {
-                        const int t = 16 * k + 8 * (l / 32) + j;
-                        const double h = t < NH ? hrows[g * MF_GROUP + l % 32][t] : 0.0;
-                        const uint16_t hi = bf16_rne((float)h);
-                        const uint16_t lo = bf16_rne((float)(h - (double)bf16_value(hi)));
-                        ha[((((g * KB + k) * 2 + 0) * 64) + l) * 8 + j] = hi;
-                        ha[((((g * KB + k) * 2 + 1) * 64) + l) * 8 + j] = lo;
-                    }
-        if ((e = hipMalloc(&c->d_pha, ha.size() * sizeof(uint16_t))) != hipSuccess) return RLBM_ENOMEM;
-        if ((e = hipMemcpy(c->d_pha, ha.data(), ha.size() * sizeof(uint16_t), hipMemcpyHostToDevice)) != hipSuccess) {
             err = hipGetErrorString(e);
             return RLBM_EDEVICE;
         }
@@ -1073,12 +912,10 @@ void push_free(rlbm_ctx c)
     if (c->d_paddr) (void)hipFree(c->d_paddr);
     if (c->d_pseg) (void)hipFree(c->d_pseg);
     if (c->d_pytab) (void)hipFree(c->d_pytab);
-    if (c->d_pha) (void)hipFree(c->d_pha);
     c->d_prec = nullptr;
     c->d_paddr = nullptr;
     c->d_pseg = nullptr;
     c->d_pytab = nullptr;
-    c->d_pha = nullptr;
     c->pvalid = 0;
 }
 
@@ -1123,7 +960,6 @@ PushParams make_push_params(rlbm_ctx c)
     P.prec = c->d_prec;
     P.seg = static_cast<const PSeg*>(c->d_pseg);
     P.ytab = c->d_pytab;
-    P.hatab = c->d_pha;
     P.G = c->d_G;
     P.Pc = c->d_Pc;
     P.nx = c->nx; P.ny = c->ny; P.Np = c->q.Np; P.bcx = c->bcx; P.bcy = c->bcy;

@@ -444,7 +444,6 @@ struct rlbm_ctx_s {
     // per-shell moment sums Z of the field output
     void* cf[2] = {nullptr, nullptr};
     void* d_pytab = nullptr;
-    void* d_pha = nullptr;               // bfloat16 deviations: matrix-core operand table of the push kernel
     double* d_dz = nullptr;
 };
 

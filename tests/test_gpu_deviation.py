@@ -195,8 +195,8 @@ def test_precision_form_quadrature_deviation_after_1000_steps():
 
 
 BF16_CASES = [
-    # (Np, K, N): a group of 32 velocities padded from 5 per segment, one
-    # block of 16 harmonics (orders 3 and 5, 2N + 5 <= 15), two blocks (order 7)
+    # (Np, K, N): 5 to 11 velocities per segment (padded to a load batch),
+    # one case per order class
     (4, 20, 3),
     (6, 40, 5),
     (8, 44, 7),
@@ -204,12 +204,10 @@ BF16_CASES = [
 
 
 @pytest.mark.parametrize("Np,K,N", BF16_CASES, ids=["order%d" % c[2] for c in BF16_CASES])
-def test_bf16dev_matrix_core_series_within_the_rounding_bound(Np, K, N):
-    """BF16DEV takes the corner-series term sum_t D_t H_t of every velocity
-    from bfloat16 matrix-core products (high and low parts, about 2^-16
-    relative), in groups of 32 velocities and blocks of 16 harmonics.  On
-    ragged segments (K / 4 velocities, padded to 32) and at every order
-    class, 30 steps stay within the stochastic-rounding bound derived in
+def test_bf16dev_within_the_rounding_bound_at_every_order(Np, K, N):
+    """BF16DEV on ragged segments and at every order class (each its own
+    kernel instance, with its own register allocation): 30 steps stay within
+    the stochastic-rounding bound derived in
     test_precision_form_quadrature_deviation_after_1000_steps, 4 x 2^-8
     sqrt(steps) / sqrt(K), against F64DEV (which equals the oracle to
     1e-12)."""
@@ -217,13 +215,13 @@ def test_bf16dev_matrix_core_series_within_the_rounding_bound(Np, K, N):
     nx, ny, steps = 150, 9, 30
     fld = W.quadrant(nx, ny, seed=3)
     tau = 1.5
-    say("case bf16dev_matrix_core Np=%d K=%d N=%d %dx%d" % (Np, K, N, nx, ny))
+    say("case bf16dev_orders Np=%d K=%d N=%d %dx%d" % (Np, K, N, nx, ny))
     ref, _ = gpu(rl, Np, K, N, nx, ny, fld, tau, 1.0, steps, "f64dev")
     got, _ = gpu(rl, Np, K, N, nx, ny, fld, tau, 1.0, steps, "bf16dev")
     e_n, e_eps, _ = field_errors(got, ref)
     du = float(np.hypot(got[2] - ref[2], got[3] - ref[3]).max())
     bound = 4 * 2.0 ** -8 * math.sqrt(steps) / math.sqrt(K)
-    say("bf16dev_matrix_core N=%d n=%.3e eps=%.3e |du|=%.3e bound %.3e" % (N, e_n, e_eps, du, bound))
+    say("bf16dev_orders N=%d n=%.3e eps=%.3e |du|=%.3e bound %.3e" % (N, e_n, e_eps, du, bound))
     assert e_n <= bound and e_eps <= bound and du <= bound, (e_n, e_eps, du, bound)
     assert e_n > 0.0
 
