@@ -417,15 +417,18 @@ __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __rest
             // of the current state
             T cc[NT];
             if (!INIT) {
-                // deviation storage: the frame as opaque values, once per
-                // shell.  Otherwise the compiler hoists the shell-independent
-                // FP64 factors of the coefficients (the polynomials in U^0)
-                // out of the shell loop and holds them through every velocity
-                // batch: about 60 more VGPRs, 2 waves per SIMD instead of 3.
-                // (The plain forms keep the hoisting: at 3 waves per SIMD
-                // they are where extra waves cost L2 reuse.)
+                // The frame as opaque values, once per shell.  Otherwise the
+                // compiler hoists the shell-independent FP64 factors of the
+                // coefficients (the polynomials in U^0) out of the shell loop
+                // and holds them through every velocity batch: 50 to 100 more
+                // VGPRs, which leaves the deviation forms, FP64 and order 7 at
+                // 2 waves per SIMD.  The plain FP32 order-5 instance keeps the
+                // hoisting: at 158 VGPRs it holds 3 waves per SIMD, its
+                // measured optimum (a fourth wave costs L2 reuse of the halo
+                // lines).
+                constexpr bool HOIST = !DEV && sizeof(T) == 4 && NM == 5;
                 double sn = fn_, sT = fT, sU0 = fU0, sUx = fUx, sUy = fUy;
-                if (DEV) asm volatile("" : "+v"(sn), "+v"(sT), "+v"(sU0), "+v"(sUx), "+v"(sUy));
+                if (!HOIST) asm volatile("" : "+v"(sn), "+v"(sT), "+v"(sU0), "+v"(sUx), "+v"(sUy));
                 shell_coeffs<NM>(Gtab + (size_t)i * GS, Pc, sn, sT, sU0, sUx, sUy,
                                  [&](int mm, double cm, double sm) __attribute__((always_inline)) {
                                      if (!ok) cm = sm = 0.0;
