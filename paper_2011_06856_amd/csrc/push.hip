@@ -422,11 +422,12 @@ __device__ __forceinline__ void push_tile(const ST* __restrict__ fin, ST* __rest
                 // coefficients (the polynomials in U^0) out of the shell loop
                 // and holds them through every velocity batch: 50 to 100 more
                 // VGPRs, which leaves the deviation forms, FP64 and order 7 at
-                // 2 waves per SIMD.  The plain FP32 order-5 instance keeps the
-                // hoisting: at 158 VGPRs it holds 3 waves per SIMD, its
-                // measured optimum (a fourth wave costs L2 reuse of the halo
-                // lines).
-                constexpr bool HOIST = !DEV && sizeof(T) == 4 && NM == 5;
+                // 2 waves per SIMD.  The plain FP32 instances of orders 3 and 5
+                // keep the hoisting (less FP64 work per site): at order 5 the
+                // 158 VGPRs give 3 waves per SIMD, the measured optimum (a
+                // fourth wave costs L2 reuse of the halo lines), and at order 3
+                // both forms give 4.
+                constexpr bool HOIST = !DEV && sizeof(T) == 4 && NM <= 5;
                 double sn = fn_, sT = fT, sU0 = fU0, sUx = fUx, sUy = fUy;
                 if (!HOIST) asm volatile("" : "+v"(sn), "+v"(sT), "+v"(sU0), "+v"(sUx), "+v"(sUy));
                 shell_coeffs<NM>(Gtab + (size_t)i * GS, Pc, sn, sT, sU0, sUx, sUy,
