@@ -88,6 +88,12 @@ def test_invalid_arguments_are_rejected_without_a_device():
     assert L.rlbm_init_quadrature(ctypes.byref(h), 4, 64, 0, 1) == R.RLBM_EINVAL
     assert L.rlbm_init_quadrature(ctypes.byref(h), 4, 64, 8, 1) == R.RLBM_EINVAL
     assert L.rlbm_init_quadrature(ctypes.byref(h), 4, 64, 3, 1) == R.RLBM_OK
+    # batch calls on a null handle
+    iv = ctypes.c_int()
+    assert L.rlbm_batch_set_push_bands(None, 2) == R.RLBM_EINVAL
+    assert L.rlbm_batch_get_push_bands(None, ctypes.byref(iv)) == R.RLBM_EINVAL
+    assert L.rlbm_batch_set_mode(None, 0) == R.RLBM_EINVAL
+    assert L.rlbm_batch_step(None, 1) == R.RLBM_EINVAL
     nx, ny = 4, 3
     n = np.ones(nx * ny)
     T = np.ones(nx * ny)
