@@ -8,6 +8,7 @@
 // weights are what Adam updates.  Parameters are one flat FP32 vector
 // [W1 (h x in), b1, W2 (h x h), b2, ..., Wout (out x h), bout], W row-major
 // [out][in].
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -39,9 +40,13 @@ __device__ inline float ld_w(const unsigned short* p, long i) { return bf2f(p[i]
 // register r of lane l is C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
+// Split K: work-group z of the grid's third dimension takes k in
+// [z kslice, (z + 1) kslice) and writes its partial product to C + z M N
+// (kslice a multiple of 16; one slice: the whole K, C itself).
 template <bool TA, bool TB, typename TBt>
 __global__ __launch_bounds__(256) void k_gemm_mfma(const float* __restrict__ A, const TBt* __restrict__ B,
-                                                   float* __restrict__ C, int M, int N, int K, int accumulate)
+                                                   float* __restrict__ C, int M, int N, int K, int accumulate,
+                                                   int kslice)
 {
     __shared__ float As[16][64 + 4];
     __shared__ float Bs[16][64 + 4];
@@ -49,19 +54,21 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const float* __restrict__ A, 
     const int lane = tid & 63, w = tid >> 6;
     const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
     const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    const int kb = blockIdx.z * kslice, ke = min(K, kb + kslice);
+    C += (long)blockIdx.z * M * N;
     floatx16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-    for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int k0 = kb; k0 < ke; k0 += 16) {
         for (int e = tid; e < 16 * 64; e += 256) {
             const int kk = e / 64, mm = e % 64;
             const int gm = m0 + mm, gk = k0 + kk;
             float va = 0.f;
-            if (gm < M && gk < K) va = TA ? A[(long)gk * M + gm] : A[(long)gm * K + gk];
+            if (gm < M && gk < ke) va = TA ? A[(long)gk * M + gm] : A[(long)gm * K + gk];
             As[kk][mm] = va;
             const int gn = n0 + mm;
             float vb = 0.f;
-            if (gn < N && gk < K) vb = TB ? ld_w(B, (long)gn * K + gk) : ld_w(B, (long)gk * N + gn);
+            if (gn < N && gk < ke) vb = TB ? ld_w(B, (long)gn * K + gk) : ld_w(B, (long)gk * N + gn);
             Bs[kk][mm] = vb;
         }
         __syncthreads();
@@ -82,6 +89,16 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const float* __restrict__ A, 
             *c = accumulate ? *c + acc[r] : acc[r];
         }
     }
+}
+
+// C[i] (+)= sum over the S slices of P[z][i], in slice order (deterministic).
+__global__ void k_sum_slices(const float* __restrict__ P, float* __restrict__ C, int S, long mn, int accumulate)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= mn) return;
+    float s = accumulate ? C[i] : 0.f;
+    for (int z = 0; z < S; ++z) s += P[(long)z * mn + i];
+    C[i] = s;
 }
 
 __device__ inline float gelu(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
@@ -390,6 +407,7 @@ struct rlbm_mlp_s {
     float* stats = nullptr;
     double* partial = nullptr;
     float* norm = nullptr;   // in_mu[7], in_sig[7], out_mu[out], out_sig[out] (out <= 8)
+    float* gpart = nullptr;  // split-K partial weight gradients [MLP_SLICES][max dout x din]
     float extra = 0.f;       // input column 63 (a per-run input, e.g. log10 Kn)
     int adam_t = 0;
     std::string err;
@@ -407,7 +425,27 @@ template <bool TA, bool TB, typename TBt>
 hipError_t gemm(hipStream_t st, const float* A, const TBt* B, float* C, int M, int N, int K, int acc)
 {
     dim3 grid((N + 63) / 64, (M + 63) / 64);
-    hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TBt>), grid, dim3(256), 0, st, A, B, C, M, N, K, acc);
+    hipLaunchKernelGGL((k_gemm_mfma<TA, TB, TBt>), grid, dim3(256), 0, st, A, B, C, M, N, K, acc, K);
+    return hipGetLastError();
+}
+
+// The weight gradients (a few 64 x 64 output tiles, K = the batch's rows):
+// K split into up to MLP_SLICES slices of at least 64 rows, so that the grid
+// fills the chip, then the slices summed in order.
+constexpr int MLP_SLICES = 64;
+
+hipError_t gemm_wgrad(hipStream_t st, float* part, const float* A, const float* B, float* C, int M, int N, int K)
+{
+    const int S = std::max(1, std::min(MLP_SLICES, K / 64));
+    if (S == 1) return gemm<true, false, float>(st, A, B, C, M, N, K, 0);
+    const int kslice = ((K + S - 1) / S + 15) / 16 * 16;
+    const int Su = (K + kslice - 1) / kslice;   // slices actually used
+    dim3 grid((N + 63) / 64, (M + 63) / 64, Su);
+    hipLaunchKernelGGL((k_gemm_mfma<true, false, float>), grid, dim3(256), 0, st, A, B, part, M, N, K, 0, kslice);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const long mn = (long)M * N;
+    hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, st, part, C, Su, mn, 0);
     return hipGetLastError();
 }
 
@@ -522,6 +560,11 @@ int rlbm_mlp_create(rlbm_mlp* out, int in_dim, int hidden, int n_hidden, int out
     al((void**)&m->stats, (size_t)max_batch * 8 * 4);
     al((void**)&m->partial, (size_t)nblk((long)max_batch * (out_dim > 1 ? out_dim : 1)) * 8);
     al((void**)&m->norm, 64 * 4);
+    {
+        size_t mn = 0;
+        for (int l = 0; l <= n_hidden; ++l) mn = std::max(mn, (size_t)m->din[l] * m->dout[l]);
+        al((void**)&m->gpart, MLP_SLICES * mn * 4);
+    }
     if (e == hipSuccess) e = hipMemset(m->m1, 0, m->np * 4);
     if (e == hipSuccess) e = hipMemset(m->m2, 0, m->np * 4);
     if (e == hipSuccess) e = hipMemset(m->p, 0, m->np * 4);
@@ -612,7 +655,7 @@ int rlbm_mlp_grad(rlbm_mlp m, const float* dX, const float* dT, int B, double* l
     for (int l = L - 1; l >= 0 && e == hipSuccess; --l) {
         const float* in = l == 0 ? dX : m->A + (size_t)(l - 1) * m->maxb * m->hid;
         // dW_l = dZ^T in ; db_l = column sums of dZ
-        e = gemm<true, false, float>(m->st, dcur, in, m->g + m->woff[l], m->dout[l], m->din[l], B, 0);
+        e = gemm_wgrad(m->st, m->gpart, dcur, in, m->g + m->woff[l], m->dout[l], m->din[l], B);
         if (e != hipSuccess) break;
         hipLaunchKernelGGL(k_colsum, dim3(m->dout[l]), dim3(256), 0, m->st, dcur, m->g + m->boff[l], (long)B,
                            m->dout[l]);
@@ -780,7 +823,8 @@ int rlbm_mlp_destroy(rlbm_mlp m)
 {
     if (!m) return RLBM_EINVAL;
     if (m->st) (void)hipStreamSynchronize(m->st);
-    void* ps[] = {m->p, m->g, m->m1, m->m2, m->pbf, m->Z, m->A, m->Y, m->dY, m->dH, m->X, m->stats, m->partial, m->norm};
+    void* ps[] = {m->p,  m->g,  m->m1,    m->m2,      m->pbf,  m->Z,   m->A,    m->Y,
+                  m->dY, m->dH, m->X, m->stats, m->partial, m->norm, m->gpart};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     delete m;

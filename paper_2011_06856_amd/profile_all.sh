@@ -56,3 +56,20 @@ python3 -m paper_2011_06856_amd.profile_summary --stats $D/stats --name batch_st
     --step-kernels k_batch_step,k_batch_flat,k_push_batch --steps 40 --sv-per-step $SV \
     --command "rocprofv3 --kernel-trace --stats -- python3 -m paper_2011_06856_amd.profile_run --workload batch48 --steps 40 (bash paper_2011_06856_amd/profile_all.sh)"
 { echo; echo "Program output: \`$(grep profile_run: $D.out.txt)\`"; } >> $OUT/batch_step_f32_batch48.md
+
+# The learned form's readout network (FP32 matrix cores): kernel statistics and
+# one pass of SQ counters, summarised for the fused inference kernel and for
+# the training GEMM.
+D=$OUT/raw/mlp
+MLPSQ="SQ_WAVES SQ_INSTS_VALU SQ_INSTS_MFMA SQ_VALU_MFMA_BUSY_CYCLES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_ANY"
+mkdir -p $D
+timeout -s KILL 180 rocprofv3 --kernel-trace --stats -d $D/stats -o run --output-format csv -- \
+    python3 -m paper_2011_06856_amd.profile_run --workload mlp --side 512 --steps 20 > $D.out.txt
+timeout -s KILL 120 rocprofv3 --pmc $MLPSQ -d $D/sq -o run --output-format csv -- \
+    python3 -m paper_2011_06856_amd.profile_run --workload mlp --side 512 --steps 5
+for k in k_mlp_fused k_gemm_mfma; do
+    python3 -m paper_2011_06856_amd.profile_summary --stats $D/stats --sq $D/sq --name mlp_${k#k_}_512 \
+        --kernel $k --launch-bytes 0 --out-dir $OUT \
+        --command "rocprofv3 --kernel-trace --stats -- python3 -m paper_2011_06856_amd.profile_run --workload mlp --side 512 --steps 20 ; rocprofv3 --pmc $MLPSQ -- python3 -m paper_2011_06856_amd.profile_run --workload mlp --side 512 --steps 5 (bash paper_2011_06856_amd/profile_all.sh)"
+    { echo; echo "Program output: \`$(grep profile_run: $D.out.txt)\`"; } >> $OUT/mlp_${k#k_}_512.md
+done

@@ -5,7 +5,10 @@ Np=4 x K=64, order 3, Kn=0.01) or, with `--workload quadrant`, of the
 quadrant Riemann problem (side^2, Np=6 x K=256, order 5, Kn=10) at the given
 precision, or, with `--workload batch48`, of the 48-problem batch (FP32, one
 graph replay per step; `--waves` sets its work-group shape, else the
-library's default), then a device-to-device
+library's default), or, with `--workload mlp`, `--steps` applications of the
+learned form's readout network to a side^2 coarse run (64-128-128-128-4,
+fused inference) and `--steps` training steps on 4096 rows (GEMMs, Adam),
+then a device-to-device
 copy of exactly `--copy-mib` MiB (read once, written once) whose FETCH_SIZE /
 WRITE_SIZE readings calibrate the counters to bytes.
 
@@ -16,6 +19,8 @@ WRITE_SIZE readings calibrate the counters to bytes.
 import argparse
 import os
 import sys
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
@@ -39,7 +44,7 @@ def main():
     ap.add_argument("--side", type=int, default=1024)
     ap.add_argument("--Kn", type=float, default=0.01)
     ap.add_argument("--copy-mib", type=int, default=1024)
-    ap.add_argument("--workload", default="circular", choices=["circular", "quadrant", "batch48"])
+    ap.add_argument("--workload", default="circular", choices=["circular", "quadrant", "batch48", "mlp"])
     ap.add_argument("--waves", type=int, default=0)
     a = ap.parse_args()
     import torch
@@ -56,6 +61,32 @@ def main():
         torch.cuda.empty_cache()
         copy_calibration(a.copy_mib)
         print("profile_run: %d steps of %s, then one %d MiB device copy" % (a.steps, what, a.copy_mib), flush=True)
+        return
+    if a.workload == "mlp":
+        side = a.side
+        cfg = W.circular_shock(side, Kn=1.0, steps=10)
+        s = rlbm.Solver(4, 24, 3)
+        s.init_fields(side, side, *cfg["fields"], tau=cfg["tau"], dt=cfg["dt"], precision="f32")
+        s.step(10)
+        net = rlbm.MLP(max_batch=side * side, out_dim=4)
+        net.init_params(seed=1)
+        # untrained weights: outputs scaled small, so that the corrected
+        # fields stay physical
+        net.set_norm(np.zeros(64), np.ones(64), np.zeros(4), np.full(4, 1e-4))
+        for _ in range(a.steps):
+            net.readout(s, 0.5)
+        g = torch.Generator(device="cpu").manual_seed(0)
+        X = torch.randn(4096, 64, generator=g).cuda()
+        T = torch.randn(4096, 4, generator=g).cuda()
+        for _ in range(a.steps):
+            net.grad(X, T)
+            net.adam_step()
+        torch.cuda.synchronize()
+        del net, s
+        torch.cuda.empty_cache()
+        copy_calibration(a.copy_mib)
+        print("profile_run: %d readouts of a %d^2 coarse run and %d training steps of the readout network, then one "
+              "%d MiB device copy" % (a.steps, side, a.steps, a.copy_mib), flush=True)
         return
     if a.workload == "circular":
         cfg = W.circular_shock(a.side, Kn=a.Kn, steps=a.steps)
