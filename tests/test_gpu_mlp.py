@@ -310,7 +310,7 @@ def test_readout_matches_oracle_forward():
 
 
 @pytest.mark.slow
-@pytest.mark.timeout(600)   # data collection and training take about two minutes
+@pytest.mark.timeout(600)   # data collection and training take over a minute
 def test_trained_readout_gains_on_held_out_seeds():
     """What the trained network gains over the method without it, on runs it
     never saw: the readout network is trained (by the library's forward,
