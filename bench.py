@@ -143,8 +143,9 @@ def batched_form(a):
     b = rlbm.Batch(probs, precision="f32")
     waves, tune_ms = b.autotune(candidates=(2, 3, 4, 6, 8), steps=4,
                                 cache=os.path.join(ROOT, "_tune_cache.json") if a.tune_cache else None,
-                                key="batch48_seed0_gfx950_f32_modes")
+                                key="batch48_seed0_gfx950_f32_modes_bands")
     mode = b.get_mode()
+    bands = b.get_push_bands()
     b.step(a.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -168,6 +169,7 @@ def batched_form(a):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batch48_uneven_shocks_np4", "problems": len(probs),
                    "site_velocities_per_step": sv / a.steps, "autotuned_waves": waves, "autotuned_mode": mode,
+                   "autotuned_push_bands": bands,
                    "fields_finite": bool(finite)},
         "batched_vs_plain": {"batched_gsvups_events": sv / (ms * 1e-3) / 1e9,
                              "plain_sequential_gsvups": sv / (plain_ms * 1e-3) / 1e9,

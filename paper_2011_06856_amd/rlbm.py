@@ -356,10 +356,10 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            self.views = []
-            lib().rlbm_batch_destroy(h)
-            self._h = None
+        self.views = []
+        if h and _L is not None:
+            _L.rlbm_batch_destroy(h)
+        self._h = None
 
     def _check(self, rc):
         if rc != RLBM_OK:
